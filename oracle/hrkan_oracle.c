@@ -1,0 +1,525 @@
+/*
+ * hrkan_oracle.c -- plain FP64 CPU oracle for one HRKAN physics-informed
+ * training step. TEST INFRASTRUCTURE ONLY (see hrkan_oracle.h).
+ *
+ * Everything here is the definition written out, point by point, in double
+ * precision:
+ *   basis  (Sec. 3, Eq. 2):   v(z) = c_m * ReLU(e - z)^m * ReLU(z - s)^m,
+ *                              c_m = (2 / (e - s))^(2m)
+ *   derivatives:              Leibniz rule on the product of the two powers
+ *   supports (Sec. 2.1-2.2):  those of the n = G + k order-k B-splines on a
+ *                              uniform grid of G intervals over [lo, hi]
+ *   layer (Sec. 3):           u_j = sum_i sum_b W[i*n_b + b][j] * v_b(z_i)
+ *   jets:                     chain rule for first and second derivatives
+ *   residual, loss (Sec. 4.1, 4.2): L = alpha * mean(r^2) + mean((u - g)^2)
+ *   gradient:                 reverse mode through the same expressions
+ *
+ * Terms whose basis factor is exactly zero (z outside the open support) are
+ * skipped; that changes no value.
+ *
+ * Parallelism: OpenMP over points. Weight gradients are summed into one
+ * buffer per thread (static schedule), then added in thread order.
+ */
+#include "hrkan_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------ */
+/* grid and basis                                                      */
+/* ------------------------------------------------------------------ */
+
+static int net_ok(const hro_net *net)
+{
+    if (!net || net->n_layers < 1 || net->n_layers > HRO_MAX_LAYERS) return 0;
+    if (net->widths[0] != 2 || net->widths[net->n_layers] != 1) return 0;
+    for (int l = 0; l <= net->n_layers; ++l)
+        if (net->widths[l] < 1) return 0;
+    if (net->G < 1 || net->k < 0 || net->m < 1) return 0;
+    if (!(net->hi > net->lo)) return 0;
+    return 1;
+}
+
+int hro_n_basis(const hro_net *net) { return net->G + net->k; }
+
+void hro_supports(const hro_net *net, double *s, double *e)
+{
+    /* Knots of the order-k B-spline basis on G uniform intervals, extended
+     * by k intervals on each side; basis b lives on knots b .. b+k+1. */
+    const int nb = hro_n_basis(net);
+    const double h = (net->hi - net->lo) / net->G;
+    for (int b = 0; b < nb; ++b) {
+        s[b] = net->lo + (double)(b - net->k) * h;
+        e[b] = net->lo + (double)(b + 1) * h;
+    }
+}
+
+static double falling(int m, int j)  /* m! / (m - j)! */
+{
+    double f = 1.0;
+    for (int t = 0; t < j; ++t) f *= (double)(m - t);
+    return f;
+}
+
+static double binom(int n, int j)
+{
+    double c = 1.0;
+    for (int t = 1; t <= j; ++t) c = c * (double)(n - j + t) / (double)t;
+    return c;
+}
+
+void hro_basis(int m, double s, double e, double z, int nmax, double *out)
+{
+    for (int n = 0; n <= nmax; ++n) out[n] = 0.0;
+    if (!(z > s && z < e)) return;               /* a ReLU factor is zero */
+    const double c = pow(2.0 / (e - s), 2.0 * m);
+    const double a = z - s;                       /* ReLU(z - s)  */
+    const double be = e - z;                      /* ReLU(e - z)  */
+    for (int n = 0; n <= nmax; ++n) {
+        double sum = 0.0;
+        for (int j = 0; j <= n; ++j) {
+            const int i = n - j;                  /* derivatives on (e - z)^m */
+            if (j > m || i > m) continue;
+            const double da = falling(m, j) * pow(a, m - j);
+            const double db = falling(m, i) * pow(be, m - i) * ((i & 1) ? -1.0 : 1.0);
+            sum += binom(n, j) * da * db;
+        }
+        out[n] = c * sum;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* one point through one layer                                         */
+/* ------------------------------------------------------------------ */
+
+/* zin: [5][win] for one point, zout: [5][wout]. */
+static void fwd_point(int m, int nb, const double *s, const double *e,
+                      int win, int wout, const double *W,
+                      const double *zin, double *zout)
+{
+    for (int q = 0; q < HRO_SLOTS * wout; ++q) zout[q] = 0.0;
+    for (int i = 0; i < win; ++i) {
+        const double z = zin[0 * win + i];
+        const double zx = zin[1 * win + i], zxx = zin[2 * win + i];
+        const double zy = zin[3 * win + i], zyy = zin[4 * win + i];
+        for (int b = 0; b < nb; ++b) {
+            if (!(z > s[b] && z < e[b])) continue;
+            double ph[3];
+            hro_basis(m, s[b], e[b], z, 2, ph);
+            const double A[HRO_SLOTS] = {
+                ph[0],
+                ph[1] * zx,
+                ph[2] * zx * zx + ph[1] * zxx,
+                ph[1] * zy,
+                ph[2] * zy * zy + ph[1] * zyy,
+            };
+            const double *wrow = W + (size_t)(i * nb + b) * wout;
+            for (int j = 0; j < wout; ++j)
+                for (int q = 0; q < HRO_SLOTS; ++q)
+                    zout[q * wout + j] += wrow[j] * A[q];
+        }
+    }
+}
+
+/* Reverse of fwd_point. ybar: [5][wout]; zbar: [5][win] (overwritten, may
+ * be NULL); gW accumulated. */
+static void bwd_point(int m, int nb, const double *s, const double *e,
+                      int win, int wout, const double *W,
+                      const double *zin, const double *ybar,
+                      double *zbar, double *gW)
+{
+    if (zbar)
+        for (int q = 0; q < HRO_SLOTS * win; ++q) zbar[q] = 0.0;
+    for (int i = 0; i < win; ++i) {
+        const double z = zin[0 * win + i];
+        const double zx = zin[1 * win + i], zxx = zin[2 * win + i];
+        const double zy = zin[3 * win + i], zyy = zin[4 * win + i];
+        for (int b = 0; b < nb; ++b) {
+            if (!(z > s[b] && z < e[b])) continue;
+            double ph[4];
+            hro_basis(m, s[b], e[b], z, 3, ph);
+            const double A[HRO_SLOTS] = {
+                ph[0],
+                ph[1] * zx,
+                ph[2] * zx * zx + ph[1] * zxx,
+                ph[1] * zy,
+                ph[2] * zy * zy + ph[1] * zyy,
+            };
+            const size_t row = (size_t)(i * nb + b);
+            const double *wrow = W + row * wout;
+            double *grow = gW + row * wout;
+            double Ab[HRO_SLOTS] = {0, 0, 0, 0, 0};
+            for (int j = 0; j < wout; ++j) {
+                double g = 0.0;
+                for (int q = 0; q < HRO_SLOTS; ++q) {
+                    const double yb = ybar[q * wout + j];
+                    Ab[q] += wrow[j] * yb;       /* dL/dA = W * dL/dY   */
+                    g += A[q] * yb;              /* dL/dW = A * dL/dY   */
+                }
+                grow[j] += g;
+            }
+            if (!zbar) continue;
+            /* A depends on (z, zx, zxx, zy, zyy) through the basis value
+             * and its derivatives; differentiate each feature. */
+            zbar[0 * win + i] += Ab[0] * ph[1]
+                               + Ab[1] * ph[2] * zx
+                               + Ab[2] * (ph[3] * zx * zx + ph[2] * zxx)
+                               + Ab[3] * ph[2] * zy
+                               + Ab[4] * (ph[3] * zy * zy + ph[2] * zyy);
+            zbar[1 * win + i] += Ab[1] * ph[1] + Ab[2] * 2.0 * ph[2] * zx;
+            zbar[2 * win + i] += Ab[2] * ph[1];
+            zbar[3 * win + i] += Ab[3] * ph[1] + Ab[4] * 2.0 * ph[2] * zy;
+            zbar[4 * win + i] += Ab[4] * ph[1];
+        }
+    }
+}
+
+static void gather(const double *src, int w, int64_t n, int64_t p, double *dst)
+{
+    for (int q = 0; q < HRO_SLOTS; ++q)
+        for (int i = 0; i < w; ++i)
+            dst[q * w + i] = src[((int64_t)q * w + i) * n + p];
+}
+
+static void scatter(const double *src, int w, int64_t n, int64_t p, double *dst)
+{
+    for (int q = 0; q < HRO_SLOTS; ++q)
+        for (int i = 0; i < w; ++i)
+            dst[((int64_t)q * w + i) * n + p] = src[q * w + i];
+}
+
+static void point_input(const double *x, int64_t p, double *z /* [5][2] */)
+{
+    /* z_0 = x, z_1 = y (or t); d/dx0 z_0 = 1, d/dx1 z_1 = 1 */
+    z[0] = x[2 * p];  z[1] = x[2 * p + 1];
+    z[2] = 1.0;       z[3] = 0.0;
+    z[4] = 0.0;       z[5] = 0.0;
+    z[6] = 0.0;       z[7] = 1.0;
+    z[8] = 0.0;       z[9] = 0.0;
+}
+
+void hro_input_jets(const double *x, int64_t n, double *zin)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        double z[10];
+        point_input(x, p, z);
+        scatter(z, 2, n, p, zin);
+    }
+}
+
+static int max_width(const hro_net *net)
+{
+    int w = 0;
+    for (int l = 0; l <= net->n_layers; ++l)
+        if (net->widths[l] > w) w = net->widths[l];
+    return w;
+}
+
+/* ------------------------------------------------------------------ */
+/* teacher-forced single layers                                        */
+/* ------------------------------------------------------------------ */
+
+int hro_layer_forward(const hro_net *net, int layer, const double *W,
+                      const double *zin, int64_t n, double *zout)
+{
+    if (!net_ok(net) || layer < 0 || layer >= net->n_layers) return -1;
+    const int nb = hro_n_basis(net), win = net->widths[layer],
+              wout = net->widths[layer + 1];
+    double *s = malloc(sizeof(double) * nb), *e = malloc(sizeof(double) * nb);
+    hro_supports(net, s, e);
+#pragma omp parallel
+    {
+        double *a = malloc(sizeof(double) * HRO_SLOTS * win);
+        double *y = malloc(sizeof(double) * HRO_SLOTS * wout);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            gather(zin, win, n, p, a);
+            fwd_point(net->m, nb, s, e, win, wout, W, a, y);
+            scatter(y, wout, n, p, zout);
+        }
+        free(a); free(y);
+    }
+    free(s); free(e);
+    return 0;
+}
+
+int hro_layer_backward(const hro_net *net, int layer, const double *W,
+                       const double *zin, const double *ybar, int64_t n,
+                       double *zbar, double *gW)
+{
+    if (!net_ok(net) || layer < 0 || layer >= net->n_layers) return -1;
+    const int nb = hro_n_basis(net), win = net->widths[layer],
+              wout = net->widths[layer + 1];
+    const size_t np = (size_t)win * nb * wout;
+    double *s = malloc(sizeof(double) * nb), *e = malloc(sizeof(double) * nb);
+    hro_supports(net, s, e);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    double *part = calloc((size_t)nt * np, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *a = malloc(sizeof(double) * HRO_SLOTS * win);
+        double *yb = malloc(sizeof(double) * HRO_SLOTS * wout);
+        double *zb = malloc(sizeof(double) * HRO_SLOTS * win);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            gather(zin, win, n, p, a);
+            gather(ybar, wout, n, p, yb);
+            bwd_point(net->m, nb, s, e, win, wout, W, a, yb, zb, part + (size_t)tid * np);
+            if (zbar) scatter(zb, win, n, p, zbar);
+        }
+        free(a); free(yb); free(zb);
+    }
+    for (int t = 0; t < nt; ++t)
+        for (size_t q = 0; q < np; ++q) gW[q] += part[(size_t)t * np + q];
+    free(part); free(s); free(e);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* whole network                                                       */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double *jets;      /* per layer l: [5][w_l], concatenated */
+    double *bar_a, *bar_b;
+    size_t off[HRO_MAX_LAYERS + 1];
+} point_ws;
+
+static void ws_init(const hro_net *net, point_ws *w)
+{
+    size_t tot = 0;
+    for (int l = 0; l <= net->n_layers; ++l) {
+        w->off[l] = tot;
+        tot += (size_t)HRO_SLOTS * net->widths[l];
+    }
+    w->jets = malloc(sizeof(double) * tot);
+    w->bar_a = malloc(sizeof(double) * HRO_SLOTS * max_width(net));
+    w->bar_b = malloc(sizeof(double) * HRO_SLOTS * max_width(net));
+}
+
+static void ws_free(point_ws *w)
+{
+    free(w->jets); free(w->bar_a); free(w->bar_b);
+}
+
+static void net_fwd_point(const hro_net *net, const double *const *W,
+                          const double *s, const double *e,
+                          const double *x, int64_t p, point_ws *w)
+{
+    const int nb = hro_n_basis(net);
+    point_input(x, p, w->jets + w->off[0]);
+    for (int l = 0; l < net->n_layers; ++l)
+        fwd_point(net->m, nb, s, e, net->widths[l], net->widths[l + 1], W[l],
+                  w->jets + w->off[l], w->jets + w->off[l + 1]);
+}
+
+/* seed: [5] bars of the output jets. gW accumulated. */
+static void net_bwd_point(const hro_net *net, const double *const *W,
+                          const double *s, const double *e,
+                          const double *seed, point_ws *w, double *const *gW)
+{
+    const int nb = hro_n_basis(net);
+    double *cur = w->bar_a, *nxt = w->bar_b;
+    for (int q = 0; q < HRO_SLOTS; ++q) cur[q] = seed[q];
+    for (int l = net->n_layers - 1; l >= 0; --l) {
+        bwd_point(net->m, nb, s, e, net->widths[l], net->widths[l + 1], W[l],
+                  w->jets + w->off[l], cur, l > 0 ? nxt : NULL, gW[l]);
+        double *t = cur; cur = nxt; nxt = t;
+    }
+}
+
+int hro_forward(const hro_net *net, const double *const *W, const double *x,
+                int64_t n, double *u_jets, double *all_jets)
+{
+    if (!net_ok(net) || n < 0) return -1;
+    const int nb = hro_n_basis(net), L = net->n_layers;
+    double *s = malloc(sizeof(double) * nb), *e = malloc(sizeof(double) * nb);
+    hro_supports(net, s, e);
+    size_t blk[HRO_MAX_LAYERS + 1], acc = 0;
+    for (int l = 0; l <= L; ++l) { blk[l] = acc; acc += (size_t)HRO_SLOTS * net->widths[l] * n; }
+#pragma omp parallel
+    {
+        point_ws w;
+        ws_init(net, &w);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            net_fwd_point(net, W, s, e, x, p, &w);
+            if (u_jets)
+                for (int q = 0; q < HRO_SLOTS; ++q)
+                    u_jets[(int64_t)q * n + p] = w.jets[w.off[L] + q];
+            if (all_jets)
+                for (int l = 0; l <= L; ++l)
+                    scatter(w.jets + w.off[l], net->widths[l], n, p, all_jets + blk[l]);
+        }
+        ws_free(&w);
+    }
+    free(s); free(e);
+    return 0;
+}
+
+static double poisson_source(double x, double y)
+{
+    /* nabla^2 u = -2 pi^2 sin(pi x) sin(pi y)  (Sec. 4.1, Eq. 3) */
+    return 2.0 * PI * PI * sin(PI * x) * sin(PI * y);
+}
+
+/* Residual of one interior point from its output jets j[5] (slot order). */
+static double residual_point(const hro_pde *pde, const double *xp,
+                             const double *j)
+{
+    if (pde->kind == HRO_POISSON2D)
+        return j[2] + j[4] + poisson_source(xp[0], xp[1]);
+    /* u_t + adv * u * u_x - nu * u_xx  (Sec. 4.2, Eq. 5 and Eq. 6) */
+    return j[3] + pde->adv * j[0] * j[1] - pde->nu * j[2];
+}
+
+/* dL/d(jets) of one interior point, given rho = dL/dr. */
+static void seed_point(const hro_pde *pde, const double *j, double rho,
+                       double *sd)
+{
+    for (int q = 0; q < HRO_SLOTS; ++q) sd[q] = 0.0;
+    if (pde->kind == HRO_POISSON2D) {
+        sd[2] = rho;                       /* dr/du_xx = 1 */
+        sd[4] = rho;                       /* dr/du_yy = 1 */
+    } else {
+        sd[0] = rho * pde->adv * j[1];     /* dr/du    = adv * u_x */
+        sd[1] = rho * pde->adv * j[0];     /* dr/du_x  = adv * u   */
+        sd[2] = -rho * pde->nu;            /* dr/du_xx = -nu       */
+        sd[3] = rho;                       /* dr/du_t  = 1         */
+    }
+}
+
+int hro_residual(const hro_pde *pde, const double *x_int,
+                 const double *jets_int, int64_t n_int,
+                 const double *u_bc, const double *g_bc, int64_t n_bc,
+                 double *r, double *loss, double *seed_int, double *seed_bc)
+{
+    if (!pde || (pde->kind != HRO_POISSON2D && pde->kind != HRO_BURGERS1D)) return -1;
+    double spde = 0.0, sbc = 0.0;
+    for (int64_t p = 0; p < n_int; ++p) {
+        double j[HRO_SLOTS];
+        for (int q = 0; q < HRO_SLOTS; ++q) j[q] = jets_int[(int64_t)q * n_int + p];
+        const double rp = residual_point(pde, x_int + 2 * p, j);
+        if (r) r[p] = rp;
+        spde += rp * rp;
+        if (seed_int) {
+            double sd[HRO_SLOTS];
+            seed_point(pde, j, 2.0 * pde->alpha * rp / (double)n_int, sd);
+            for (int q = 0; q < HRO_SLOTS; ++q) seed_int[(int64_t)q * n_int + p] = sd[q];
+        }
+    }
+    for (int64_t p = 0; p < n_bc; ++p) {
+        const double d = u_bc[p] - g_bc[p];
+        sbc += d * d;
+        if (seed_bc) seed_bc[p] = 2.0 * d / (double)n_bc;
+    }
+    const double lpde = n_int > 0 ? spde / (double)n_int : 0.0;
+    const double lbc = n_bc > 0 ? sbc / (double)n_bc : 0.0;
+    loss[0] = pde->alpha * lpde + lbc;
+    loss[1] = lpde;
+    loss[2] = lbc;
+    return 0;
+}
+
+int hro_backward(const hro_net *net, const double *const *W, const double *x,
+                 int64_t n, const double *seed, double *const *gW)
+{
+    if (!net_ok(net) || n < 0) return -1;
+    const int nb = hro_n_basis(net), L = net->n_layers;
+    double *s = malloc(sizeof(double) * nb), *e = malloc(sizeof(double) * nb);
+    hro_supports(net, s, e);
+    size_t np[HRO_MAX_LAYERS], tot = 0;
+    for (int l = 0; l < L; ++l) { np[l] = (size_t)net->widths[l] * nb * net->widths[l + 1]; tot += np[l]; }
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    double *part = calloc((size_t)nt * tot, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *mine[HRO_MAX_LAYERS];
+        size_t o = (size_t)tid * tot;
+        for (int l = 0; l < L; ++l) { mine[l] = part + o; o += np[l]; }
+        point_ws w;
+        ws_init(net, &w);
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            double sd[HRO_SLOTS];
+            for (int q = 0; q < HRO_SLOTS; ++q) sd[q] = seed[(int64_t)q * n + p];
+            net_fwd_point(net, W, s, e, x, p, &w);
+            net_bwd_point(net, W, s, e, sd, &w, mine);
+        }
+        ws_free(&w);
+    }
+    for (int t = 0; t < nt; ++t) {
+        size_t o = (size_t)t * tot;
+        for (int l = 0; l < L; ++l) {
+            for (size_t q = 0; q < np[l]; ++q) gW[l][q] += part[o + q];
+            o += np[l];
+        }
+    }
+    free(part); free(s); free(e);
+    return 0;
+}
+
+int hro_step(const hro_net *net, const hro_pde *pde, const double *const *W,
+             const double *x_int, int64_t n_int,
+             const double *x_bc, int64_t n_bc, const double *g_bc,
+             double *loss, double *const *gW,
+             double *r_out, double *jets_out, double *ubc_out)
+{
+    if (!net_ok(net) || !pde || n_int < 0 || n_bc < 0) return -1;
+    if (pde->kind != HRO_POISSON2D && pde->kind != HRO_BURGERS1D) return -1;
+    const int nb = hro_n_basis(net), L = net->n_layers;
+    for (int l = 0; l < L; ++l)
+        memset(gW[l], 0, sizeof(double) * (size_t)net->widths[l] * nb * net->widths[l + 1]);
+
+    /* forward jets at every point */
+    double *ji = malloc(sizeof(double) * HRO_SLOTS * (size_t)(n_int > 0 ? n_int : 1));
+    double *jb = malloc(sizeof(double) * HRO_SLOTS * (size_t)(n_bc > 0 ? n_bc : 1));
+    if (hro_forward(net, W, x_int, n_int, ji, NULL)) return -1;
+    if (hro_forward(net, W, x_bc, n_bc, jb, NULL)) return -1;
+
+    /* residual, loss and seeds */
+    double *si = malloc(sizeof(double) * HRO_SLOTS * (size_t)(n_int > 0 ? n_int : 1));
+    double *sbc = malloc(sizeof(double) * (size_t)(n_bc > 0 ? n_bc : 1));
+    double *sb = calloc(HRO_SLOTS * (size_t)(n_bc > 0 ? n_bc : 1), sizeof(double));
+    hro_residual(pde, x_int, ji, n_int, jb /* slot 0 = u */, g_bc, n_bc,
+                 r_out, loss, si, sbc);
+    for (int64_t p = 0; p < n_bc; ++p) sb[p] = sbc[p];   /* only du is seeded */
+
+    /* reverse: gW = dL/dW summed over both point sets */
+    hro_backward(net, W, x_int, n_int, si, gW);
+    hro_backward(net, W, x_bc, n_bc, sb, gW);
+
+    if (jets_out) memcpy(jets_out, ji, sizeof(double) * HRO_SLOTS * (size_t)n_int);
+    if (ubc_out) memcpy(ubc_out, jb, sizeof(double) * (size_t)n_bc);
+    free(ji); free(jb); free(si); free(sbc); free(sb);
+    return 0;
+}
+
+int hro_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,123 @@
+/*
+ * hrkan_oracle.h -- plain FP64 CPU oracle for one physics-informed training
+ * step of a Higher-order-ReLU KAN (HRKAN).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. It shares no source,
+ * header, table or helper with the GPU library and must never be used as a
+ * fallback for it.
+ *
+ * What it computes (all in double precision, scalar loops, no tiling):
+ *   - the HR basis of order m and its derivatives (Sec. 3, Eq. 2),
+ *   - the KAN layer as "basis tensor times weight matrix" (Sec. 3, the
+ *     matrix-operation remark; Sec. 2.2 for the supports),
+ *   - forward-mode jets (value, first and second derivative per input
+ *     direction) through every layer, as needed by the PDE residuals
+ *     (Sec. 4.1 loss, Sec. 4.2 loss),
+ *   - the residuals and the loss L = alpha*L_pde + L_bc (Sec. 4.1 and 4.2),
+ *   - the exact reverse-mode gradient of L with respect to every weight.
+ *
+ * Jet layout used throughout: five slots per feature,
+ *   slot 0 = value, 1 = d/dx0, 2 = d2/dx0^2, 3 = d/dx1, 4 = d2/dx1^2,
+ * where x0 is the first input coordinate (x) and x1 the second (y, or t for
+ * Burgers). Arrays of jets are [5][width][n] (slot, feature, point), doubles.
+ * Slots that a caller does not need are still computed; they cost time only.
+ *
+ * Weights of layer l: [w_l * n_b][w_{l+1}] row-major, row index i*n_b + b
+ * (input feature i, basis function b), n_b = G + k.
+ */
+#ifndef HRKAN_ORACLE_H
+#define HRKAN_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HRO_MAX_LAYERS 8
+#define HRO_SLOTS 5
+
+typedef struct {
+    int32_t n_layers;                     /* number of KAN layers L          */
+    int32_t widths[HRO_MAX_LAYERS + 1];   /* widths[0] = 2, widths[L] = 1    */
+    int32_t G;                            /* grid intervals on [lo, hi]      */
+    int32_t k;                            /* B-spline order of the supports  */
+    int32_t m;                            /* HR order                        */
+    double lo, hi;                        /* grid range                      */
+} hro_net;
+
+enum { HRO_POISSON2D = 0, HRO_BURGERS1D = 1 };
+
+typedef struct {
+    int32_t kind;    /* HRO_POISSON2D or HRO_BURGERS1D                        */
+    double nu;       /* Burgers viscosity                                    */
+    double alpha;    /* weight of the PDE term in the loss                   */
+    double adv;      /* Burgers advection coefficient (1 for u_t+u u_x-nu u_xx) */
+} hro_pde;
+
+/* n_b = G + k basis functions per input. */
+int hro_n_basis(const hro_net *net);
+
+/* Support [s_b, e_b] of every basis function b = 0..n_b-1. */
+void hro_supports(const hro_net *net, double *s, double *e);
+
+/* d^n/dz^n of the order-m HR bump on [s,e] at z, n = 0..nmax (nmax <= 8),
+ * written to out[0..nmax]. Zero outside the open interval (s, e). */
+void hro_basis(int m, double s, double e, double z, int nmax, double *out);
+
+/* Teacher-forced layer forward: zin [5][w_l][n] -> zout [5][w_{l+1}][n]. */
+int hro_layer_forward(const hro_net *net, int layer, const double *W,
+                      const double *zin, int64_t n, double *zout);
+
+/* Teacher-forced layer reverse: given the input jets zin [5][w_l][n] and the
+ * bars of the output jets ybar [5][w_{l+1}][n], write the bars of the input
+ * jets to zbar [5][w_l][n] (may be NULL) and ADD the weight gradient to gW. */
+int hro_layer_backward(const hro_net *net, int layer, const double *W,
+                       const double *zin, const double *ybar, int64_t n,
+                       double *zbar, double *gW);
+
+/* Layer-0 input jets of points x [n][2]: value x, unit first derivative
+ * along its own direction, zero second derivatives. zin is [5][2][n]. */
+void hro_input_jets(const double *x, int64_t n, double *zin);
+
+/* Whole network forward: x [n][2] -> jets of the output u, [5][n].
+ * If all_jets is not NULL it receives the jets entering every layer l = 0..L,
+ * concatenated: block l is [5][w_l][n]. */
+int hro_forward(const hro_net *net, const double *const *W, const double *x,
+                int64_t n, double *u_jets, double *all_jets);
+
+/* Residual, loss and seeds. jets_int [5][n_int] are the output jets at the
+ * interior points x_int [n_int][2]; u_bc [n_bc] are the values at the
+ * boundary/initial points with targets g_bc [n_bc].
+ * loss[0] = L, loss[1] = L_pde, loss[2] = L_bc.
+ * r [n_int], seed_int [5][n_int] (dL/d jets) and seed_bc [n_bc] (dL/du) may
+ * be NULL. */
+int hro_residual(const hro_pde *pde, const double *x_int,
+                 const double *jets_int, int64_t n_int,
+                 const double *u_bc, const double *g_bc, int64_t n_bc,
+                 double *r, double *loss, double *seed_int, double *seed_bc);
+
+/* Whole network reverse: given seeds [5][n] on the output jets of points
+ * x [n][2], ADD dL/dW of every layer to gW[l]. */
+int hro_backward(const hro_net *net, const double *const *W, const double *x,
+                 int64_t n, const double *seed, double *const *gW);
+
+/* One full step: forward jets at interior and boundary points, residual,
+ * loss, and the gradient of L with respect to every weight. gW[l] is
+ * OVERWRITTEN. r_out [n_int], jets_out [5][n_int] and ubc_out [n_bc] may be
+ * NULL. */
+int hro_step(const hro_net *net, const hro_pde *pde, const double *const *W,
+             const double *x_int, int64_t n_int,
+             const double *x_bc, int64_t n_bc, const double *g_bc,
+             double *loss, double *const *gW,
+             double *r_out, double *jets_out, double *ubc_out);
+
+/* Number of OpenMP threads the oracle runs with. */
+int hro_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,257 @@
+"""ctypes wrapper of the FP64 CPU oracle (hrkan_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark. It shares nothing with the GPU library and
+is never a fallback for it.
+
+Jet arrays are [5][width][n] float64 with slots
+(value, d/dx0, d2/dx0^2, d/dx1, d2/dx1^2); the output jets of the network are
+[5][n]. Weights of layer l are [w_l * n_b, w_{l+1}] float64, row i*n_b + b.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hrkan_oracle.c")
+_LIB = os.path.join(_HERE, "libhrkan_oracle.so")
+
+MAX_LAYERS = 8
+SLOTS = 5
+POISSON2D = 0
+BURGERS1D = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (strict IEEE double, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "hrkan_oracle.h"))
+    ):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+             "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Net(ctypes.Structure):
+    _fields_ = [
+        ("n_layers", ctypes.c_int32),
+        ("widths", ctypes.c_int32 * (MAX_LAYERS + 1)),
+        ("G", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("lo", ctypes.c_double),
+        ("hi", ctypes.c_double),
+    ]
+
+
+class _Pde(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("nu", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("adv", ctypes.c_double),
+    ]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.POINTER
+        i64 = ctypes.c_int64
+        lib.hro_n_basis.argtypes = [P(_Net)]
+        lib.hro_supports.argtypes = [P(_Net), _D, _D]
+        lib.hro_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, _D]
+        lib.hro_layer_forward.argtypes = [P(_Net), ctypes.c_int, _D, _D, i64, _D]
+        lib.hro_layer_backward.argtypes = [P(_Net), ctypes.c_int, _D, _D, _D, i64, _D, _D]
+        lib.hro_input_jets.argtypes = [_D, i64, _D]
+        lib.hro_forward.argtypes = [P(_Net), P(_D), _D, i64, _D, _D]
+        lib.hro_residual.argtypes = [P(_Pde), _D, _D, i64, _D, _D, i64, _D, _D, _D, _D]
+        lib.hro_backward.argtypes = [P(_Net), P(_D), _D, i64, _D, P(_D)]
+        lib.hro_step.argtypes = [P(_Net), P(_Pde), P(_D), _D, i64, _D, i64, _D, _D,
+                                 P(_D), _D, _D, _D]
+        lib.hro_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _net(net) -> _Net:
+    n = _Net()
+    w = list(net.widths)
+    n.n_layers = len(w) - 1
+    for i, v in enumerate(w):
+        n.widths[i] = int(v)
+    n.G, n.k, n.m = int(net.G), int(net.k), int(net.m)
+    n.lo, n.hi = float(getattr(net, "lo", -1.0)), float(getattr(net, "hi", 1.0))
+    return n
+
+
+def _pde(pde) -> _Pde:
+    p = _Pde()
+    p.kind = int(pde.kind)
+    p.nu = float(pde.nu)
+    p.alpha = float(pde.alpha)
+    p.adv = float(getattr(pde, "adv", 1.0))
+    return p
+
+
+def _wlist(Ws):
+    Ws = [_f64(w) for w in Ws]
+    arr = (_D * len(Ws))(*[_ptr(w) for w in Ws])
+    return Ws, arr
+
+
+def num_threads() -> int:
+    return _load().hro_num_threads()
+
+
+def n_basis(net) -> int:
+    return int(net.G) + int(net.k)
+
+
+def supports(net):
+    nb = n_basis(net)
+    s = np.zeros(nb)
+    e = np.zeros(nb)
+    n = _net(net)
+    _load().hro_supports(ctypes.byref(n), _ptr(s), _ptr(e))
+    return s, e
+
+
+def basis(m: int, s: float, e: float, z: float, nmax: int = 3) -> np.ndarray:
+    out = np.zeros(nmax + 1)
+    _load().hro_basis(int(m), float(s), float(e), float(z), int(nmax), _ptr(out))
+    return out
+
+
+def input_jets(x) -> np.ndarray:
+    x = _f64(x)
+    n = x.shape[0]
+    z = np.zeros((SLOTS, 2, n))
+    _load().hro_input_jets(_ptr(x), n, _ptr(z))
+    return z
+
+
+def layer_forward(net, layer: int, W, zin) -> np.ndarray:
+    zin = _f64(zin)
+    n = zin.shape[-1]
+    wout = list(net.widths)[layer + 1]
+    zout = np.zeros((SLOTS, wout, n))
+    nn = _net(net)
+    W = _f64(W)
+    rc = _load().hro_layer_forward(ctypes.byref(nn), layer, _ptr(W), _ptr(zin), n, _ptr(zout))
+    assert rc == 0
+    return zout
+
+
+def layer_backward(net, layer: int, W, zin, ybar, want_zbar: bool = True):
+    zin = _f64(zin)
+    ybar = _f64(ybar)
+    n = zin.shape[-1]
+    W = _f64(W)
+    gW = np.zeros_like(W)
+    zbar = np.zeros_like(zin) if want_zbar else None
+    nn = _net(net)
+    rc = _load().hro_layer_backward(ctypes.byref(nn), layer, _ptr(W), _ptr(zin), _ptr(ybar),
+                                    n, _ptr(zbar), _ptr(gW))
+    assert rc == 0
+    return zbar, gW
+
+
+def forward(net, Ws, x, all_jets: bool = False):
+    """Output jets [5][n]; with all_jets, also the list of per-layer input jets."""
+    x = _f64(x)
+    n = x.shape[0]
+    Ws, arr = _wlist(Ws)
+    u = np.zeros((SLOTS, n))
+    widths = list(net.widths)
+    blocks = None
+    if all_jets:
+        tot = sum(SLOTS * w * n for w in widths)
+        blocks = np.zeros(tot)
+    nn = _net(net)
+    rc = _load().hro_forward(ctypes.byref(nn), arr, _ptr(x), n, _ptr(u), _ptr(blocks))
+    assert rc == 0
+    if not all_jets:
+        return u
+    out, o = [], 0
+    for w in widths:
+        out.append(blocks[o:o + SLOTS * w * n].reshape(SLOTS, w, n))
+        o += SLOTS * w * n
+    return u, out
+
+
+def residual(pde, x_int, jets_int, u_bc, g_bc):
+    """(r [n_int], loss [3], seed_int [5][n_int], seed_bc [n_bc])."""
+    x_int = _f64(x_int)
+    jets_int = _f64(jets_int)
+    u_bc = _f64(u_bc)
+    g_bc = _f64(g_bc)
+    ni, nbc = x_int.shape[0], u_bc.shape[0]
+    r = np.zeros(ni)
+    loss = np.zeros(3)
+    si = np.zeros((SLOTS, ni))
+    sb = np.zeros(nbc)
+    p = _pde(pde)
+    rc = _load().hro_residual(ctypes.byref(p), _ptr(x_int), _ptr(jets_int), ni, _ptr(u_bc),
+                              _ptr(g_bc), nbc, _ptr(r), _ptr(loss), _ptr(si), _ptr(sb))
+    assert rc == 0
+    return r, loss, si, sb
+
+
+def backward(net, Ws, x, seed):
+    x = _f64(x)
+    seed = _f64(seed)
+    n = x.shape[0]
+    Ws, arr = _wlist(Ws)
+    gWs = [np.zeros_like(w) for w in Ws]
+    garr = (_D * len(gWs))(*[_ptr(g) for g in gWs])
+    nn = _net(net)
+    rc = _load().hro_backward(ctypes.byref(nn), arr, _ptr(x), n, _ptr(seed), garr)
+    assert rc == 0
+    return gWs
+
+
+def step(net, pde, Ws, x_int, x_bc, g_bc):
+    """One full step: dict with loss [3], gW list, r, jets [5][n_int], u_bc."""
+    x_int = _f64(x_int)
+    x_bc = _f64(x_bc)
+    g_bc = _f64(g_bc)
+    ni, nbc = x_int.shape[0], x_bc.shape[0]
+    Ws, arr = _wlist(Ws)
+    gWs = [np.zeros_like(w) for w in Ws]
+    garr = (_D * len(gWs))(*[_ptr(g) for g in gWs])
+    loss = np.zeros(3)
+    r = np.zeros(ni)
+    jets = np.zeros((SLOTS, ni))
+    ubc = np.zeros(nbc)
+    nn = _net(net)
+    p = _pde(pde)
+    rc = _load().hro_step(ctypes.byref(nn), ctypes.byref(p), arr, _ptr(x_int), ni, _ptr(x_bc),
+                          nbc, _ptr(g_bc), _ptr(loss), garr, _ptr(r), _ptr(jets), _ptr(ubc))
+    assert rc == 0
+    return {"loss": loss, "gW": gWs, "r": r, "jets": jets, "u_bc": ubc}
