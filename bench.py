@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of one HRKAN physics-informed training step on one MI355X.
+
+A step is the whole hot path over one batch of synthetic collocation points:
+forward jets at the interior and boundary points, residual and loss, and the
+reverse pass to every weight (hrkan_step). Default workload: viscous Burgers
+(nu = 0.01/pi) with a [2,32,32,1] HRKAN, G = 10, k = 3, m = 4, 65,536 interior
++ 4,096 initial/boundary points, FP32.
+
+Prints ONE JSON line: interior collocation points per second over the timed
+steps (inputs resident in HBM), the roofline position of the dominant kernel
+(timed per launch with HIP events on the step's stream), and the CPU oracle
+timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PINN train-step collocation points/s (fwd jets+residual+bwd), bf16 vs fp32"
+
+# MI355X published peaks
+PEAK = {
+    "hbm_GBs": 8000.0,
+    "mfma_f32": 157.3, "mfma_f64": 78.6, "mfma_bf16": 2500.0,
+    # vector ALU without packed FP32: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+    "alu_f32": 78.6, "alu_f64": 78.6,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="burgers_c2")
+    ap.add_argument("--dtype", default=None, help="f64 | f32 | bf16 (default: the workload's)")
+    ap.add_argument("--bf16-split", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def layer_flops(net, C, n, dense=True):
+    """Algorithmic flops of the three contractions of each layer for n points
+    with C jet channels: 2*C*K*N per point and contraction, K = w_in * n_b
+    (dense basis tensor, as the method states it)."""
+    out = {}
+    for l in range(net.n_layers):
+        K = net.widths[l] * (net.n_basis if dense else (net.k + 1))
+        N = net.widths[l + 1]
+        f = 2.0 * C * K * N * n
+        out[f"fwd_l{l}"] = f
+        out[f"dw_l{l}"] = f
+        if l > 0:
+            out[f"dx_l{l}"] = f
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the data-parallel design over several GPUs is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2409_14248_amd import hrkan as H
+    from paper_2409_14248_amd import workloads as WL
+
+    wl = WL.WORKLOADS[args.workload]
+    dtype = args.dtype or wl.dtype
+    pr = WL.make_problem(wl)
+    step = H.Step(pr, dtype, args.bf16_split)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    loss = step.loss.cpu().numpy()
+
+    # per-kernel times over a second timed pass (events around every launch)
+    H.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = H.profile_read()
+    H.profile_enable(False)
+
+    C = H.mask_channels(H.pde_mask(pr.pde.kind))
+    dense = {k: v + layer_flops(pr.net, 1, pr.n_bc).get(k, 0.0)
+             for k, v in layer_flops(pr.net, C, pr.n_int).items()}
+    total_ms = sum(v[1] for v in prof.values()) / args.steps
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (dcnt, dms) = dom
+    per_launch_ms = dms / dcnt
+    launches_per_step = dcnt / args.steps
+    flops_per_launch = dense.get(dname, 0.0) / launches_per_step
+    kind = {"f64": "f64", "f32": "f32", "bf16": "bf16"}[dtype]
+    if dtype == "bf16":
+        bound, peak = "mfma", PEAK["mfma_bf16"]
+    else:
+        bound, peak = "mfma", PEAK[f"mfma_{kind}"]
+    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": bound, "kernel": dname, "achieved": round(achieved, 3), "peak": peak,
+        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+        "launch_ms": round(per_launch_ms, 5), "flops_per_launch": flops_per_launch,
+        "kernel_share": round(dms / args.steps / total_ms, 3),
+    }
+    step_flops = sum(dense.values())
+
+    cpu = None
+    if not args.no_cpu:
+        sys.path.insert(0, os.path.join(ROOT, "oracle"))
+        import oracle as O
+        q = pr.rounded(np.float32 if dtype != "f64" else np.float64)
+        t = time.time()
+        reps = 0
+        while True:
+            O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
+            reps += 1
+            el = time.time() - t
+            if el >= args.cpu_seconds or reps >= 3:
+                break
+        cpu = {"value": round(reps * pr.n_int / el, 1), "unit": "points/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": f"{reps} full step(s) of {args.workload} ({pr.n_int}+{pr.n_bc} points), "
+                         f"FP64, {el:.1f} s"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(pr.n_int / (ms * 1e-3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "pde": "poisson2d" if pr.pde.kind == 0 else "burgers1d",
+            "widths": list(pr.net.widths), "G": pr.net.G, "k": pr.net.k, "m": pr.net.m,
+            "n_int": pr.n_int, "n_bc": pr.n_bc,
+            **({"bf16_split": args.bf16_split} if dtype == "bf16" else {}),
+        },
+        "total_points_per_s": round((pr.n_int + pr.n_bc) / (ms * 1e-3), 1),
+        "step_dense_tflops": round(step_flops / (ms * 1e-3) / 1e12, 3),
+        "loss": [float(v) for v in loss],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 5) for k, v in sorted(prof.items())},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * hrkan.h -- C ABI of the MI355X (gfx950) library for one physics-informed
+ * training step of a Higher-order-ReLU KAN (HRKAN, So & Yung).
+ *
+ * The step (Sec. 3 and Sec. 4 of the paper):
+ *   1. every KAN layer evaluates, for each input feature z_i, the HR basis
+ *        v_b(z) = c_m * ReLU(e_b - z)^m * ReLU(z - s_b)^m,  c_m = (2/(e_b-s_b))^(2m)
+ *      (Sec. 3, Eq. 2) on the supports of the order-k B-splines of a uniform
+ *      grid of G intervals on [lo, hi] (Sec. 2.1-2.2; n_b = G + k functions),
+ *      and contracts the basis tensor [points x (w_in * n_b)] with the layer's
+ *      weight matrix [w_in * n_b, w_out] (the matrix operation of Sec. 3);
+ *   2. the value is carried together with its first and second derivatives
+ *      along each input coordinate (forward jets) through every layer;
+ *   3. the PDE residual and the loss L = alpha * L_pde + L_bc are formed
+ *      (Poisson: Sec. 4.1, Eq. 3 and its loss; viscous Burgers: Sec. 4.2,
+ *      Eq. 5/6 and Eq. 7);
+ *   4. L is differentiated back to every weight (reverse mode through the
+ *      jets, with the basis recomputed rather than stored).
+ *
+ * Conventions shared by every call
+ *   - Every array argument is DEVICE memory owned by the caller, unless the
+ *     argument says "host". The library never allocates device memory in these
+ *     calls; scratch lives in the caller's workspace `ws`.
+ *   - Calls are asynchronous on `stream` (0 = the null stream). They validate
+ *     every argument on the host before anything is enqueued and return a
+ *     status code; no C++ exception crosses this interface. A non-zero code
+ *     means nothing was enqueued, except HRKAN_ERR_DEVICE (a HIP launch error;
+ *     the stream may hold part of the work).
+ *   - Results are deterministic run to run on one device: every reduction has
+ *     a fixed order and no floating-point atomics are used.
+ *   - Calls are re-entrant for distinct workspaces. Two calls in flight on the
+ *     same workspace race. The first 256 bytes of a workspace hold the device
+ *     status word (hrkan_read_status): zero them once before first use.
+ *   - Floating-point arrays use the "array type" of the network's dtype:
+ *       HRKAN_F64  -> double;
+ *       HRKAN_F32  -> float;
+ *       HRKAN_BF16 -> float (FP32 master weights and FP32 jets; the basis x W
+ *                     contractions run on BF16 matrix cores, see bf16_split).
+ *   - Points x are [n][2] row-major: (x, y) for Poisson, (x, t) for Burgers.
+ *   - Jets are channel-major [C][n]; the channels present are the set bits of
+ *     a channel mask, in the order U, X, XX, Y, YY (X = d/dx0, Y = d/dx1,
+ *     where x1 is y for Poisson and t for Burgers).
+ *   - Weights of layer l are [w_l * n_b][w_{l+1}] row-major, row i*n_b + b for
+ *     input feature i and basis function b. Weight gradients use the same
+ *     layout and the array type.
+ */
+#ifndef HRKAN_H
+#define HRKAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HRKAN_MAX_LAYERS 8
+#define HRKAN_MAX_WIDTH 1024
+
+/* status codes */
+#define HRKAN_OK 0
+#define HRKAN_ERR_INVALID_ARG (-1)   /* null/misaligned pointer, bad size, bad field */
+#define HRKAN_ERR_UNSUPPORTED (-2)   /* valid but not implemented: dtype, m, mask, width */
+#define HRKAN_ERR_WORKSPACE (-3)     /* ws_bytes smaller than required */
+#define HRKAN_ERR_DEVICE (-4)        /* a HIP call failed; see hrkan_last_error() */
+#define HRKAN_ERR_PLAN_MISMATCH (-5) /* plan used with another shape or freed */
+
+/* bits of the device status word (hrkan_read_status) */
+#define HRKAN_STATUS_NONFINITE 1u    /* a loss partial was NaN or Inf */
+
+/* contraction precision (hrkan_net_desc.dtype) */
+#define HRKAN_F64 0
+#define HRKAN_F32 1
+#define HRKAN_BF16 2
+
+/* PDE kinds (hrkan_pde_desc.kind) */
+#define HRKAN_POISSON2D 0   /* u_xx + u_yy = -2 pi^2 sin(pi x) sin(pi y), Sec. 4.1 Eq. 3 */
+#define HRKAN_BURGERS1D 1   /* u_t + adv * u * u_x - nu * u_xx = 0, Sec. 4.2 Eq. 5 / Eq. 6 */
+
+/* jet channels */
+#define HRKAN_CH_U 1u
+#define HRKAN_CH_X 2u
+#define HRKAN_CH_XX 4u
+#define HRKAN_CH_Y 8u
+#define HRKAN_CH_YY 16u
+#define HRKAN_MASK_POISSON (HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_XX | HRKAN_CH_Y | HRKAN_CH_YY)
+#define HRKAN_MASK_BURGERS (HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_XX | HRKAN_CH_Y)
+#define HRKAN_MASK_VALUE HRKAN_CH_U
+
+/* Network description (host struct).
+ *   n_layers   1..HRKAN_MAX_LAYERS; widths[0] = 2, widths[n_layers] = 1,
+ *              every width in 1..HRKAN_MAX_WIDTH.
+ *   G, k, m    grid intervals (>= 1), B-spline order of the supports (0..8),
+ *              HR order (2..8; the paper uses m = 4). Every layer uses the
+ *              same grid [lo, hi] (lo < hi).
+ *   dtype      HRKAN_F64, HRKAN_F32 or HRKAN_BF16.
+ *   bf16_split number of BF16 product terms S for HRKAN_BF16 (1, 2 or 3):
+ *              1: a_hi*b_hi; 2: adds a_lo*b_hi (the weight is used in BF16,
+ *              the basis/bar operand in two BF16 pieces); 3: also adds
+ *              a_hi*b_lo (both operands split). Ignored for F32/F64.          */
+typedef struct {
+    int32_t n_layers;
+    int32_t widths[HRKAN_MAX_LAYERS + 1];
+    int32_t G, k, m;
+    double lo, hi;
+    int32_t dtype;
+    int32_t bf16_split;
+} hrkan_net_desc;
+
+/* PDE description (host struct). alpha weighs L_pde in L = alpha L_pde + L_bc
+ * (the paper uses 0.05). For Burgers, nu is the viscosity and adv the
+ * coefficient of u*u_x (1 for Eq. 5; 1/4 with nu/16 for the rescaled Eq. 6). */
+typedef struct {
+    int32_t kind;
+    double nu;
+    double alpha;
+    double adv;
+} hrkan_pde_desc;
+
+/* Collocation sets (host struct holding device pointers).
+ *   x_int [n_int][2]   interior points (residual)
+ *   x_bc  [n_bc][2]    boundary / initial points (value misfit)
+ *   g_bc  [n_bc]       target values at x_bc (0 on walls, the initial
+ *                      condition on t = 0)
+ * Either count may be 0 (the pointer may then be NULL); the matching loss
+ * term is then 0. */
+typedef struct {
+    const void *x_int;
+    int64_t n_int;
+    const void *x_bc;
+    int64_t n_bc;
+    const void *g_bc;
+} hrkan_points;
+
+/* Fill *net / *pde with the paper's defaults (G=5, k=3, m=4, [-1,1], F32,
+ * S=2; alpha=0.05, adv=1, nu=0.01/pi for Burgers). Returns HRKAN_OK. */
+int hrkan_net_init(hrkan_net_desc *net);
+int hrkan_pde_init(hrkan_pde_desc *pde, int32_t kind);
+
+/* Number of channels of a mask, or a negative status if the mask is not one
+ * of the supported sets (U alone; U,X,XX,Y; U,X,XX,Y,YY; U,X,Y; U,X,XX). */
+int hrkan_mask_channels(uint32_t channel_mask);
+
+/* Bytes of the `saved` buffer that hrkan_forward_jets fills and
+ * hrkan_backward reads for n points: the jets entering layers 1..L-1, in the
+ * array type, [C][w_l][n] per layer. */
+int hrkan_saved_bytes(const hrkan_net_desc *net, int64_t n, uint32_t channel_mask,
+                      size_t *bytes /* host */);
+
+/* Bytes of workspace that every call below needs for at most n_int interior
+ * and n_bc boundary points (hrkan_forward_jets / hrkan_backward with
+ * n <= max(n_int, n_bc) included). ws must be 256-byte aligned. */
+int hrkan_workspace_bytes(const hrkan_net_desc *net, const hrkan_pde_desc *pde,
+                          int64_t n_int, int64_t n_bc, size_t *bytes /* host */);
+
+/* Forward jets: the network's output u and the derivatives selected by
+ * channel_mask at n points x [n][2].
+ *   W        host array of n_layers device pointers, W[l] as documented above
+ *   jets_out [C][n] (array type)
+ *   saved    NULL, or hrkan_saved_bytes(...) bytes that receive the inner
+ *            jets needed by hrkan_backward for the same x, W and mask */
+int hrkan_forward_jets(const hrkan_net_desc *net, const void *const *W, const void *x,
+                       int64_t n, uint32_t channel_mask, void *jets_out, void *saved,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Residual, loss and seeds (Sec. 4.1 / 4.2 losses).
+ *   jets_int [C][n_int]  output jets at pts->x_int with the PDE's mask
+ *                        (HRKAN_MASK_POISSON or HRKAN_MASK_BURGERS)
+ *   u_bc     [n_bc]      network values at pts->x_bc
+ *   r_out    [n_int]     residual (may be NULL)
+ *   loss_out device double[3] = {L, L_pde, L_bc}
+ *   seed_int [C][n_int]  dL/d(jets_int) (may be NULL)
+ *   seed_bc  [n_bc]      dL/d(u_bc) (may be NULL)
+ * dtype is the array type of jets/seeds (HRKAN_F64 or HRKAN_F32; BF16 runs
+ * pass HRKAN_F32). Partial sums are reduced in double precision. */
+int hrkan_residual(const hrkan_pde_desc *pde, int32_t dtype, const void *jets_int,
+                   const void *u_bc, const hrkan_points *pts, void *r_out, double *loss_out,
+                   void *seed_int, void *seed_bc, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* Reverse pass: given seed [C][n] = dL/d(output jets) at points x, write
+ * dL/dW to gW_out[l] (host array of device pointers), overwriting it, or
+ * adding to it when accumulate != 0. `saved` is what hrkan_forward_jets
+ * wrote for the same x, W, n and mask. The basis is recomputed from the
+ * saved jets. */
+int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *x, int64_t n,
+                   uint32_t channel_mask, const void *seed, const void *saved,
+                   void *const *gW_out, int32_t accumulate, void *ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* One full training step: forward jets at both point sets, residual, loss
+ * (loss_out device double[3] = {L, L_pde, L_bc}) and gW_out[l] = dL/dW[l]
+ * (overwritten). The interior mask is the PDE's (Poisson: 5 channels,
+ * Burgers: 4); boundary points carry the value only. */
+int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
+               const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
+               size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched step: many independent instances of one network shape, each with */
+/* its own weights, PDE coefficients and point counts, run by one           */
+/* persistent kernel whose launches are captured in a HIP graph.            */
+/* ---------------------------------------------------------------------- */
+typedef struct hrkan_plan hrkan_plan;
+
+/* Create a plan (host call; may allocate host memory and run the tile
+ * autotuner, which times candidate tile shapes on `stream` with the caller's
+ * buffers; it never allocates device memory).
+ *   n_inst     number of instances (>= 1)
+ *   pdes       host array [n_inst] (kind must be HRKAN_BURGERS1D or
+ *              HRKAN_POISSON2D, one kind for all instances)
+ *   W_packed   [n_inst][n_params] weights, instance-major, each instance's
+ *              layers concatenated in order (array type)
+ *   pts        host array [n_inst] of collocation sets (device pointers)
+ *   loss_out   device double [n_inst][3]
+ *   gW_packed  [n_inst][n_params] gradients (overwritten at each execute)
+ *   ws         workspace of hrkan_plan_workspace_bytes(...) bytes
+ * The plan keeps every pointer until hrkan_plan_destroy. Only HRKAN_F32 is
+ * supported. */
+int hrkan_plan_workspace_bytes(const hrkan_net_desc *net, int32_t n_inst,
+                               const hrkan_points *pts /* host [n_inst] */,
+                               size_t *bytes /* host */);
+int hrkan_plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_inst,
+                      const hrkan_pde_desc *pdes, const void *W_packed, const hrkan_points *pts,
+                      double *loss_out, void *gW_packed, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+/* Enqueue one batched step (one graph launch) on stream. */
+int hrkan_plan_execute(hrkan_plan *plan, hipStream_t stream);
+/* Tile configuration the autotuner chose (host ints: points per tile, work
+ * items per persistent block); either pointer may be NULL. */
+int hrkan_plan_config(const hrkan_plan *plan, int32_t *tile_points, int32_t *blocks);
+void hrkan_plan_destroy(hrkan_plan *plan);
+
+/* Read and clear the device status word kept in ws (synchronises stream).
+ * *flags (host) receives a set of HRKAN_STATUS_* bits. */
+int hrkan_read_status(void *ws, size_t ws_bytes, hipStream_t stream, uint32_t *flags);
+
+/* Static description of a status code, and the detailed message of the last
+ * failing call on this host thread (empty if none). */
+const char *hrkan_status_string(int code);
+const char *hrkan_last_error(void);
+
+/* Kernel timing, for benchmarks. While enabled (on != 0), every kernel the
+ * library launches is bracketed by two HIP events recorded on the stream it
+ * runs on. hrkan_profile_read waits for those events, writes one line
+ * "<kernel> <launches> <total_ms>\n" per kernel name into buf (host,
+ * NUL-terminated, truncated to buflen) and forgets the recorded events. The
+ * names are "<stage>_l<layer>" for per-layer kernels (stage fwd, dx, dw,
+ * reduce) and plain names otherwise. Not thread-safe; off by default. */
+int hrkan_profile_enable(int32_t on);
+int hrkan_profile_read(char *buf, size_t buflen);
+
+/* ABI version (major * 100 + minor). */
+int hrkan_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRKAN_H */

@@ -32,6 +32,54 @@
 #define PI 3.14159265358979323846
 
 /* ------------------------------------------------------------------ */
+/* optional rounding model (off unless hro_set_rounding is called)      */
+/* ------------------------------------------------------------------ */
+
+static int g_mode = 0, g_split = 1;
+
+void hro_set_rounding(int mode, int split)
+{
+    g_mode = mode;
+    g_split = split < 1 ? 1 : (split > 2 ? 2 : split);
+}
+
+static double to_f32(double v) { return (double)(float)v; }
+
+/* Nearest-even rounding of a float to the 8-bit-mantissa bfloat16 grid. */
+static double to_bf16(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (double)f;   /* Inf, NaN */
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double round_feature(double a)
+{
+    if (g_mode == 0) return a;
+    a = to_f32(a);
+    if (g_mode == 2) {
+        const double hi = to_bf16(a);
+        a = g_split >= 2 ? hi + to_bf16(a - hi) : hi;
+    }
+    return a;
+}
+
+static double round_store(double v) { return g_mode == 0 ? v : to_f32(v); }
+
+/* one step of a contraction's running sum, acc + w * a; in the rounding
+ * model it is rounded to FP32 as an FP32 fused multiply-add would (the
+ * product of two FP32 values is exact in double: one rounding of the sum) */
+static double acc_step(double acc, double w, double a)
+{
+    return g_mode == 0 ? acc + w * a : to_f32(acc + w * a);
+}
+
+/* ------------------------------------------------------------------ */
 /* grid and basis                                                      */
 /* ------------------------------------------------------------------ */
 
@@ -113,18 +161,20 @@ static void fwd_point(int m, int nb, const double *s, const double *e,
             double ph[3];
             hro_basis(m, s[b], e[b], z, 2, ph);
             const double A[HRO_SLOTS] = {
-                ph[0],
-                ph[1] * zx,
-                ph[2] * zx * zx + ph[1] * zxx,
-                ph[1] * zy,
-                ph[2] * zy * zy + ph[1] * zyy,
+                round_feature(ph[0]),
+                round_feature(ph[1] * zx),
+                round_feature(ph[2] * zx * zx + ph[1] * zxx),
+                round_feature(ph[1] * zy),
+                round_feature(ph[2] * zy * zy + ph[1] * zyy),
             };
             const double *wrow = W + (size_t)(i * nb + b) * wout;
             for (int j = 0; j < wout; ++j)
                 for (int q = 0; q < HRO_SLOTS; ++q)
-                    zout[q * wout + j] += wrow[j] * A[q];
+                    zout[q * wout + j] = acc_step(zout[q * wout + j], wrow[j], A[q]);
         }
     }
+    if (g_mode)
+        for (int q = 0; q < HRO_SLOTS * wout; ++q) zout[q] = round_store(zout[q]);
 }
 
 /* Reverse of fwd_point. ybar: [5][wout]; zbar: [5][win] (overwritten, may
@@ -145,11 +195,11 @@ static void bwd_point(int m, int nb, const double *s, const double *e,
             double ph[4];
             hro_basis(m, s[b], e[b], z, 3, ph);
             const double A[HRO_SLOTS] = {
-                ph[0],
-                ph[1] * zx,
-                ph[2] * zx * zx + ph[1] * zxx,
-                ph[1] * zy,
-                ph[2] * zy * zy + ph[1] * zyy,
+                round_feature(ph[0]),
+                round_feature(ph[1] * zx),
+                round_feature(ph[2] * zx * zx + ph[1] * zxx),
+                round_feature(ph[1] * zy),
+                round_feature(ph[2] * zy * zy + ph[1] * zyy),
             };
             const size_t row = (size_t)(i * nb + b);
             const double *wrow = W + row * wout;
@@ -159,7 +209,7 @@ static void bwd_point(int m, int nb, const double *s, const double *e,
                 double g = 0.0;
                 for (int q = 0; q < HRO_SLOTS; ++q) {
                     const double yb = ybar[q * wout + j];
-                    Ab[q] += wrow[j] * yb;       /* dL/dA = W * dL/dY   */
+                    Ab[q] = acc_step(Ab[q], wrow[j], yb);   /* dL/dA = W * dL/dY */
                     g += A[q] * yb;              /* dL/dW = A * dL/dY   */
                 }
                 grow[j] += g;
@@ -178,6 +228,8 @@ static void bwd_point(int m, int nb, const double *s, const double *e,
             zbar[4 * win + i] += Ab[4] * ph[1];
         }
     }
+    if (zbar && g_mode)
+        for (int q = 0; q < HRO_SLOTS * win; ++q) zbar[q] = round_store(zbar[q]);
 }
 
 static void gather(const double *src, int w, int64_t n, int64_t p, double *dst)

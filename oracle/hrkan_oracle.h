@@ -113,6 +113,19 @@ int hro_step(const hro_net *net, const hro_pde *pde, const double *const *W,
              double *loss, double *const *gW,
              double *r_out, double *jets_out, double *ubc_out);
 
+/* Rounding model, OFF by default (mode 0: every value exact in double).
+ * It only serves to estimate how much error storage in a narrower type alone
+ * causes through the network's conditioning, for tolerance gates:
+ *   mode 1: every basis feature, every partial sum of a contraction over
+ *           the basis (as an FP32 fused multiply-add chain, in the oracle's
+ *           summation order) and every stored layer output (and input bar
+ *           in the reverse pass) is rounded to FP32;
+ *   mode 2: as mode 1, and every basis feature is further replaced by the sum
+ *           of its first `split` BF16 pieces (hi, then lo = the BF16 rounding
+ *           of the remainder), each rounded to nearest even.
+ * Weights are never rounded here: callers pass already rounded weights. */
+void hro_set_rounding(int mode, int split);
+
 /* Number of OpenMP threads the oracle runs with. */
 int hro_num_threads(void);
 

@@ -84,6 +84,8 @@ def _load():
         lib.hro_step.argtypes = [P(_Net), P(_Pde), P(_D), _D, i64, _D, i64, _D, _D,
                                  P(_D), _D, _D, _D]
         lib.hro_num_threads.restype = ctypes.c_int
+        lib.hro_set_rounding.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.hro_set_rounding.restype = None
         _lib = lib
     return _lib
 
@@ -123,6 +125,22 @@ def _wlist(Ws):
     Ws = [_f64(w) for w in Ws]
     arr = (_D * len(Ws))(*[_ptr(w) for w in Ws])
     return Ws, arr
+
+
+class rounding:
+    """Context manager enabling the oracle's rounding model (see
+    hro_set_rounding): "f32", or "bf16" with `split` pieces per feature."""
+
+    def __init__(self, mode: str, split: int = 1):
+        self.mode = {"exact": 0, "f32": 1, "bf16": 2}[mode]
+        self.split = split
+
+    def __enter__(self):
+        _load().hro_set_rounding(self.mode, self.split)
+        return self
+
+    def __exit__(self, *a):
+        _load().hro_set_rounding(0, 1)
 
 
 def num_threads() -> int:

@@ -1,0 +1,59 @@
+// internal.h -- interface between the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hr_device.h"
+#include "hrkan.h"
+
+namespace hrk {
+
+// Channel configuration of a call: orders of differentiation along x0, x1.
+struct ChanCfg {
+    int o0, o1;
+    int C() const { return 1 + o0 + o1; }
+};
+
+// One layer's shapes.
+struct LayerShape {
+    int win, wout, nb;
+};
+
+// ---- generic kernels (any supported dtype as T = float / double) ----------
+template <typename T>
+hipError_t launch_fwd_generic(ChanCfg ch, bool first, const T *zin, const T *W, T *zout,
+                              int64_t n, LayerShape ls, const GridP<T> &g, hipStream_t st);
+
+template <typename T>
+hipError_t launch_dx_generic(ChanCfg ch, const T *zin, const T *ybar, const T *W, T *zbar,
+                             int64_t n, LayerShape ls, const GridP<T> &g, hipStream_t st);
+
+// Partial weight gradients of `nsplit` point slices into part[nsplit][K*N].
+template <typename T>
+hipError_t launch_dw_generic(ChanCfg ch, bool first, const T *zin, const T *ybar, T *part,
+                             int nsplit, int64_t n, LayerShape ls, const GridP<T> &g,
+                             hipStream_t st);
+int dw_generic_splits(int64_t n, LayerShape ls);
+size_t dw_generic_lds_bytes(int elem, int C, int nb);
+
+// out[e] (+)= sum_s part[s][e] for e < count, s in fixed order.
+template <typename T>
+hipError_t launch_reduce_splits(const T *part, int nsplit, int64_t count, T *out, int accumulate,
+                                hipStream_t st);
+
+// Residual, seeds and per-block loss partials; then the final reduction.
+struct PdeParams {
+    int kind;
+    double nu, alpha, adv;
+};
+template <typename T>
+hipError_t launch_residual(const PdeParams &pde, int C, const T *jets, const T *x_int,
+                           int64_t n_int, const T *u_bc, const T *g_bc, int64_t n_bc, T *r_out,
+                           T *seed_int, T *seed_bc, double *partials, int nblk, hipStream_t st);
+int residual_blocks(int64_t n_int, int64_t n_bc);
+hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, int64_t n_bc,
+                             double alpha, double *loss_out, uint32_t *status, hipStream_t st);
+
+}  // namespace hrk

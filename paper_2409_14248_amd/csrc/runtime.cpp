@@ -1,0 +1,578 @@
+// runtime.cpp -- host side of the HRKAN C ABI: argument validation, workspace
+// layout, and the sequence of kernel launches of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "hrkan.h"
+#include "internal.h"
+#include "runtime_internal.h"
+
+namespace hrk {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(HRKAN_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_net(const hrkan_net_desc *d, NetInfo *ni)
+{
+    if (!d) return fail(HRKAN_ERR_INVALID_ARG, "net is NULL");
+    if (d->n_layers < 1 || d->n_layers > HRKAN_MAX_LAYERS)
+        return fail(HRKAN_ERR_INVALID_ARG, "n_layers=%d outside 1..%d", d->n_layers, HRKAN_MAX_LAYERS);
+    if (d->widths[0] != 2) return fail(HRKAN_ERR_INVALID_ARG, "widths[0]=%d, must be 2", d->widths[0]);
+    if (d->widths[d->n_layers] != 1)
+        return fail(HRKAN_ERR_INVALID_ARG, "widths[n_layers]=%d, must be 1", d->widths[d->n_layers]);
+    int maxw = 0;
+    for (int l = 0; l <= d->n_layers; ++l) {
+        if (d->widths[l] < 1 || d->widths[l] > HRKAN_MAX_WIDTH)
+            return fail(HRKAN_ERR_INVALID_ARG, "widths[%d]=%d outside 1..%d", l, d->widths[l], HRKAN_MAX_WIDTH);
+        maxw = std::max(maxw, d->widths[l]);
+    }
+    if (d->G < 1 || d->G > 4096) return fail(HRKAN_ERR_INVALID_ARG, "G=%d outside 1..4096", d->G);
+    if (d->k < 0 || d->k > 8) return fail(HRKAN_ERR_INVALID_ARG, "k=%d outside 0..8", d->k);
+    if (d->m < 2 || d->m > 8) return fail(HRKAN_ERR_UNSUPPORTED, "m=%d outside 2..8", d->m);
+    if (!std::isfinite(d->lo) || !std::isfinite(d->hi) || !(d->hi > d->lo))
+        return fail(HRKAN_ERR_INVALID_ARG, "grid [%g, %g] is not a finite interval", d->lo, d->hi);
+    if (d->dtype != HRKAN_F64 && d->dtype != HRKAN_F32 && d->dtype != HRKAN_BF16)
+        return fail(HRKAN_ERR_INVALID_ARG, "dtype=%d unknown", d->dtype);
+    if (d->dtype == HRKAN_BF16 && (d->bf16_split < 1 || d->bf16_split > 3))
+        return fail(HRKAN_ERR_INVALID_ARG, "bf16_split=%d outside 1..3", d->bf16_split);
+    if (d->k + 1 > 4)
+        return fail(HRKAN_ERR_UNSUPPORTED, "k=%d: at most 4 live basis functions per input (k <= 3)", d->k);
+    ni->L = d->n_layers;
+    for (int l = 0; l <= d->n_layers; ++l) ni->w[l] = d->widths[l];
+    ni->G = d->G;
+    ni->k = d->k;
+    ni->m = d->m;
+    ni->nb = d->G + d->k;
+    ni->lo = d->lo;
+    ni->hi = d->hi;
+    ni->dtype = d->dtype;
+    ni->S = d->dtype == HRKAN_BF16 ? d->bf16_split : 1;
+    ni->elem = d->dtype == HRKAN_F64 ? 8 : 4;
+    ni->maxw = maxw;
+    if (ni->nb > 32) return fail(HRKAN_ERR_UNSUPPORTED, "n_b = G + k = %d > 32", ni->nb);
+    ni->n_params = 0;
+    for (int l = 0; l < ni->L; ++l) ni->n_params += (int64_t)ni->w[l] * ni->nb * ni->w[l + 1];
+    return HRKAN_OK;
+}
+
+int mask_cfg(uint32_t mask, ChanCfg *ch)
+{
+    switch (mask) {
+    case HRKAN_CH_U: *ch = {0, 0}; return HRKAN_OK;
+    case HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_Y: *ch = {1, 1}; return HRKAN_OK;
+    case HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_XX: *ch = {2, 0}; return HRKAN_OK;
+    case HRKAN_MASK_BURGERS: *ch = {2, 1}; return HRKAN_OK;
+    case HRKAN_MASK_POISSON: *ch = {2, 2}; return HRKAN_OK;
+    default: break;
+    }
+    if (!(mask & HRKAN_CH_U) || mask > 31)
+        return fail(HRKAN_ERR_INVALID_ARG, "channel mask 0x%x: must contain U and only U,X,XX,Y,YY", mask);
+    return fail(HRKAN_ERR_UNSUPPORTED, "channel mask 0x%x is not a supported set", mask);
+}
+
+template <typename T>
+GridP<T> make_grid(const NetInfo &ni)
+{
+    const double h = (ni.hi - ni.lo) / ni.G;
+    GridP<T> g;
+    g.lo = (T)ni.lo;
+    g.inv_w = (T)(2.0 / ((ni.k + 1) * h));
+    g.kappa = (T)(2.0 / (ni.k + 1));
+    g.inv_kappa = (T)((ni.k + 1) / 2.0);
+    g.k = ni.k;
+    g.nb = ni.nb;
+    g.m = ni.m;
+    return g;
+}
+template GridP<float> make_grid<float>(const NetInfo &);
+template GridP<double> make_grid<double>(const NetInfo &);
+
+static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int64_t saved_elems(const NetInfo &ni, int C, int64_t n)
+{
+    int64_t e = 0;
+    for (int l = 1; l < ni.L; ++l) e += (int64_t)C * ni.w[l] * n;
+    return e;
+}
+
+// Slices of the weight-gradient reduction for n points at layer l.
+int dw_splits(const NetInfo &ni, int l, int64_t n)
+{
+    if (n <= 0) return 0;
+    return dw_generic_splits(n, LayerShape{ni.w[l], ni.w[l + 1], ni.nb});
+}
+
+static int64_t max_part_elems(const NetInfo &ni, int64_t n_a, int64_t n_b)
+{
+    int64_t m = 0;
+    for (int l = 0; l < ni.L; ++l) {
+        const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+        m = std::max(m, (int64_t)(dw_splits(ni, l, n_a) + dw_splits(ni, l, n_b)) * kn);
+    }
+    return m;
+}
+
+// Workspace regions, in bytes from the start of ws. Sizes use 5 channels for
+// interior sets so one layout serves both PDE kinds.
+WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
+{
+    WsLayout L{};
+    const size_t E = ni.elem;
+    const int64_t nmax = std::max<int64_t>(std::max(n_int, n_bc), 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += up256(bytes); return at; };
+    L.status = take(256);
+    L.nres = residual_blocks(n_int, n_bc);
+    L.loss_part = take(sizeof(double) * 2 * (size_t)L.nres);
+    L.sv_int = take(E * (size_t)saved_elems(ni, 5, n_int));
+    L.jets_int = take(E * 5 * (size_t)n_int);
+    L.sv_bc = take(E * (size_t)saved_elems(ni, 1, n_bc));
+    L.ubc = take(E * (size_t)n_bc);
+    L.seed_int = take(E * 5 * (size_t)n_int);
+    L.seed_bc = take(E * (size_t)n_bc);
+    L.bars0 = take(E * 5 * (size_t)ni.maxw * nmax);
+    L.bars1 = take(E * 5 * (size_t)ni.maxw * nmax);
+    L.bbars0 = take(E * (size_t)ni.maxw * n_bc);
+    L.bbars1 = take(E * (size_t)ni.maxw * n_bc);
+    L.part_elems = max_part_elems(ni, std::max(n_int, n_bc), std::min(n_int, n_bc));
+    L.part = take(E * (size_t)L.part_elems);
+    L.total = o;
+    return L;
+}
+
+}  // namespace hrk
+
+using namespace hrk;
+
+// ---------------------------------------------------------------------------
+// forward / backward bodies (array type T)
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, int64_t n,
+                 T *jets_out, T *saved, T *tmp0, T *tmp1, hipStream_t st)
+{
+    const GridP<T> g = make_grid<T>(ni);
+    const int C = ch.C();
+    const T *zin = x;
+    int64_t soff = 0;
+    for (int l = 0; l < ni.L; ++l) {
+        T *zout;
+        if (l == ni.L - 1)
+            zout = jets_out;
+        else if (saved) {
+            zout = saved + soff;
+            soff += (int64_t)C * ni.w[l + 1] * n;
+        } else
+            zout = (l % 2 == 0) ? tmp0 : tmp1;
+        hipError_t e;
+        {
+            ProfScope ps("fwd", l, st);
+            e = launch_fwd_generic<T>(ch, l == 0, zin, W[l], zout, n,
+                                      LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, g, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "forward layer launch");
+        zin = zout;
+    }
+    return HRKAN_OK;
+}
+
+// Input jets of layer l (x for l = 0, else a block of `saved`).
+template <typename T>
+const T *layer_input(const NetInfo &ni, int C, int l, const T *x, const T *saved, int64_t n)
+{
+    if (l == 0) return x;
+    int64_t off = 0;
+    for (int q = 1; q < l; ++q) off += (int64_t)C * ni.w[q] * n;
+    return saved + off;
+}
+
+// Reverse pass of up to two point sets sharing W: set A (channels chA) and
+// optionally set B (chB), each with its own seeds, saved jets and bar
+// buffers. Their weight gradients are summed into gW (fixed order: all
+// slices of A, then of B).
+template <typename T>
+struct RevSet {
+    ChanCfg ch;
+    const T *x;
+    int64_t n;
+    const T *seed;
+    const T *saved;
+    T *bar0, *bar1;
+};
+
+template <typename T>
+int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, int nsets,
+                 T *const *gW, int accumulate, T *part, hipStream_t st)
+{
+    const GridP<T> g = make_grid<T>(ni);
+    const T *ybar[2] = {nullptr, nullptr};
+    for (int s = 0; s < nsets; ++s) ybar[s] = sets[s].seed;
+    for (int l = ni.L - 1; l >= 0; --l) {
+        const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
+        const int64_t kn = (int64_t)ls.win * ls.nb * ls.wout;
+        int tot = 0;
+        for (int s = 0; s < nsets; ++s) {
+            const RevSet<T> &S = sets[s];
+            if (S.n <= 0) continue;
+            const int ns = dw_splits(ni, l, S.n);
+            const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
+            hipError_t e;
+            {
+                ProfScope ps("dw", l, st);
+                e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar[s], part + (int64_t)tot * kn, ns, S.n,
+                                         ls, g, st);
+            }
+            if (e != hipSuccess) return hip_fail(e, "weight-gradient launch");
+            tot += ns;
+        }
+        if (tot == 0) {
+            if (!accumulate) {
+                hipError_t e = launch_reduce_splits<T>(part, 0, kn, gW[l], 0, st);
+                if (e != hipSuccess) return hip_fail(e, "gW clear");
+            }
+        } else {
+            ProfScope ps("reduce", l, st);
+            hipError_t e = launch_reduce_splits<T>(part, tot, kn, gW[l], accumulate, st);
+            if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+        }
+        if (l == 0) break;
+        for (int s = 0; s < nsets; ++s) {
+            const RevSet<T> &S = sets[s];
+            if (S.n <= 0) continue;
+            T *zbar = (ybar[s] == S.bar0) ? S.bar1 : S.bar0;
+            const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
+            hipError_t e;
+            {
+                ProfScope ps("dx", l, st);
+                e = launch_dx_generic<T>(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, st);
+            }
+            if (e != hipSuccess) return hip_fail(e, "input-bar launch");
+            ybar[s] = zbar;
+        }
+    }
+    return HRKAN_OK;
+}
+
+int check_ws(void *ws, size_t ws_bytes, size_t need)
+{
+    if (!ws) return fail(HRKAN_ERR_INVALID_ARG, "ws is NULL");
+    if (!aligned(ws, 256)) return fail(HRKAN_ERR_INVALID_ARG, "ws is not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(HRKAN_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return HRKAN_OK;
+}
+
+int check_weights(const NetInfo &ni, const void *const *W, const char *what)
+{
+    if (!W) return fail(HRKAN_ERR_INVALID_ARG, "%s array is NULL", what);
+    for (int l = 0; l < ni.L; ++l) {
+        if (!W[l]) return fail(HRKAN_ERR_INVALID_ARG, "%s[%d] is NULL", what, l);
+        if (!aligned(W[l], ni.elem)) return fail(HRKAN_ERR_INVALID_ARG, "%s[%d] misaligned", what, l);
+    }
+    return HRKAN_OK;
+}
+
+int check_pde(const hrkan_pde_desc *pde)
+{
+    if (!pde) return fail(HRKAN_ERR_INVALID_ARG, "pde is NULL");
+    if (pde->kind != HRKAN_POISSON2D && pde->kind != HRKAN_BURGERS1D)
+        return fail(HRKAN_ERR_INVALID_ARG, "pde kind %d unknown", pde->kind);
+    if (!std::isfinite(pde->nu) || !std::isfinite(pde->alpha) || !std::isfinite(pde->adv))
+        return fail(HRKAN_ERR_INVALID_ARG, "pde coefficients must be finite");
+    return HRKAN_OK;
+}
+
+uint32_t pde_mask(int kind) { return kind == HRKAN_POISSON2D ? HRKAN_MASK_POISSON : HRKAN_MASK_BURGERS; }
+
+#define TRY(x)                          \
+    do {                                \
+        int rc_ = (x);                  \
+        if (rc_ != HRKAN_OK) return rc_; \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int hrkan_version(void) { return 100; }
+
+const char *hrkan_status_string(int code)
+{
+    switch (code) {
+    case HRKAN_OK: return "ok";
+    case HRKAN_ERR_INVALID_ARG: return "invalid argument";
+    case HRKAN_ERR_UNSUPPORTED: return "unsupported configuration";
+    case HRKAN_ERR_WORKSPACE: return "workspace too small";
+    case HRKAN_ERR_DEVICE: return "HIP device error";
+    case HRKAN_ERR_PLAN_MISMATCH: return "plan mismatch";
+    default: return "unknown status";
+    }
+}
+
+const char *hrkan_last_error(void) { return g_err.c_str(); }
+
+int hrkan_net_init(hrkan_net_desc *net)
+{
+    if (!net) return fail(HRKAN_ERR_INVALID_ARG, "net is NULL");
+    std::memset(net, 0, sizeof *net);
+    net->n_layers = 2;
+    net->widths[0] = 2;
+    net->widths[1] = 2;
+    net->widths[2] = 1;
+    net->G = 5;
+    net->k = 3;
+    net->m = 4;
+    net->lo = -1.0;
+    net->hi = 1.0;
+    net->dtype = HRKAN_F32;
+    net->bf16_split = 2;
+    return HRKAN_OK;
+}
+
+int hrkan_pde_init(hrkan_pde_desc *pde, int32_t kind)
+{
+    if (!pde) return fail(HRKAN_ERR_INVALID_ARG, "pde is NULL");
+    if (kind != HRKAN_POISSON2D && kind != HRKAN_BURGERS1D)
+        return fail(HRKAN_ERR_INVALID_ARG, "pde kind %d unknown", kind);
+    pde->kind = kind;
+    pde->alpha = 0.05;
+    pde->adv = 1.0;
+    pde->nu = kind == HRKAN_BURGERS1D ? 0.01 / 3.14159265358979323846 : 0.0;
+    return HRKAN_OK;
+}
+
+int hrkan_mask_channels(uint32_t channel_mask)
+{
+    ChanCfg ch;
+    TRY(mask_cfg(channel_mask, &ch));
+    return ch.C();
+}
+
+int hrkan_saved_bytes(const hrkan_net_desc *net, int64_t n, uint32_t channel_mask, size_t *bytes)
+{
+    NetInfo ni;
+    ChanCfg ch;
+    TRY(check_net(net, &ni));
+    TRY(mask_cfg(channel_mask, &ch));
+    if (n < 0) return fail(HRKAN_ERR_INVALID_ARG, "n < 0");
+    if (!bytes) return fail(HRKAN_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = ni.elem * (size_t)saved_elems(ni, ch.C(), n);
+    return HRKAN_OK;
+}
+
+int hrkan_workspace_bytes(const hrkan_net_desc *net, const hrkan_pde_desc *pde, int64_t n_int,
+                          int64_t n_bc, size_t *bytes)
+{
+    NetInfo ni;
+    TRY(check_net(net, &ni));
+    TRY(check_pde(pde));
+    if (n_int < 0 || n_bc < 0) return fail(HRKAN_ERR_INVALID_ARG, "negative point count");
+    if (!bytes) return fail(HRKAN_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = extra_ws_bytes(ni, n_int, n_bc) + layout(ni, n_int, n_bc).total;
+    return HRKAN_OK;
+}
+
+int hrkan_forward_jets(const hrkan_net_desc *net, const void *const *W, const void *x, int64_t n,
+                       uint32_t channel_mask, void *jets_out, void *saved, void *ws, size_t ws_bytes,
+                       hipStream_t stream)
+{
+    NetInfo ni;
+    ChanCfg ch;
+    TRY(check_net(net, &ni));
+    TRY(mask_cfg(channel_mask, &ch));
+    if (n < 0) return fail(HRKAN_ERR_INVALID_ARG, "n < 0");
+    TRY(check_weights(ni, W, "W"));
+    if (n > 0 && (!x || !jets_out)) return fail(HRKAN_ERR_INVALID_ARG, "x or jets_out is NULL");
+    if (x && !aligned(x, ni.elem)) return fail(HRKAN_ERR_INVALID_ARG, "x misaligned");
+    const WsLayout L = layout(ni, n, 0);
+    TRY(check_ws(ws, ws_bytes, L.total));
+    if (n == 0) return HRKAN_OK;
+    char *w = (char *)ws;
+    if (ni.dtype == HRKAN_F64)
+        return forward_impl<double>(ni, ch, (const double *const *)W, (const double *)x, n,
+                                    (double *)jets_out, (double *)saved, (double *)(w + L.bars0),
+                                    (double *)(w + L.bars1), stream);
+    if (ni.dtype == HRKAN_BF16)
+        return bf16_forward(ni, ch, W, (const float *)x, n, (float *)jets_out, (float *)saved, ws,
+                            ws_bytes, stream);
+    return forward_impl<float>(ni, ch, (const float *const *)W, (const float *)x, n,
+                               (float *)jets_out, (float *)saved, (float *)(w + L.bars0),
+                               (float *)(w + L.bars1), stream);
+}
+
+int hrkan_residual(const hrkan_pde_desc *pde, int32_t dtype, const void *jets_int, const void *u_bc,
+                   const hrkan_points *pts, void *r_out, double *loss_out, void *seed_int,
+                   void *seed_bc, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    TRY(check_pde(pde));
+    if (dtype != HRKAN_F64 && dtype != HRKAN_F32)
+        return fail(HRKAN_ERR_INVALID_ARG, "residual dtype must be HRKAN_F64 or HRKAN_F32");
+    if (!pts) return fail(HRKAN_ERR_INVALID_ARG, "pts is NULL");
+    if (pts->n_int < 0 || pts->n_bc < 0) return fail(HRKAN_ERR_INVALID_ARG, "negative point count");
+    if (pts->n_int > 0 && (!jets_int || !pts->x_int))
+        return fail(HRKAN_ERR_INVALID_ARG, "jets_int or x_int is NULL");
+    if (pts->n_bc > 0 && (!u_bc || !pts->g_bc)) return fail(HRKAN_ERR_INVALID_ARG, "u_bc or g_bc is NULL");
+    if (!loss_out) return fail(HRKAN_ERR_INVALID_ARG, "loss_out is NULL");
+    const int nblk = residual_blocks(pts->n_int, pts->n_bc);
+    const size_t need = 256 + up256(sizeof(double) * 2 * nblk);
+    TRY(check_ws(ws, ws_bytes, need));
+    char *w = (char *)ws;
+    double *partials = (double *)(w + 256);
+    const PdeParams pp{pde->kind, pde->nu, pde->alpha, pde->adv};
+    const int C = hrkan_mask_channels(pde_mask(pde->kind));
+    hipError_t e;
+    if (dtype == HRKAN_F64)
+        e = launch_residual<double>(pp, C, (const double *)jets_int, (const double *)pts->x_int,
+                                    pts->n_int, (const double *)u_bc, (const double *)pts->g_bc,
+                                    pts->n_bc, (double *)r_out, (double *)seed_int,
+                                    (double *)seed_bc, partials, nblk, stream);
+    else
+        e = launch_residual<float>(pp, C, (const float *)jets_int, (const float *)pts->x_int,
+                                   pts->n_int, (const float *)u_bc, (const float *)pts->g_bc,
+                                   pts->n_bc, (float *)r_out, (float *)seed_int, (float *)seed_bc,
+                                   partials, nblk, stream);
+    if (e != hipSuccess) return hip_fail(e, "residual launch");
+    e = launch_loss_final(partials, nblk, pts->n_int, pts->n_bc, pde->alpha, loss_out,
+                          (uint32_t *)w, stream);
+    if (e != hipSuccess) return hip_fail(e, "loss launch");
+    return HRKAN_OK;
+}
+
+int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *x, int64_t n,
+                   uint32_t channel_mask, const void *seed, const void *saved, void *const *gW_out,
+                   int32_t accumulate, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    NetInfo ni;
+    ChanCfg ch;
+    TRY(check_net(net, &ni));
+    TRY(mask_cfg(channel_mask, &ch));
+    if (n < 0) return fail(HRKAN_ERR_INVALID_ARG, "n < 0");
+    TRY(check_weights(ni, W, "W"));
+    TRY(check_weights(ni, (const void *const *)gW_out, "gW_out"));
+    if (n > 0 && (!x || !seed)) return fail(HRKAN_ERR_INVALID_ARG, "x or seed is NULL");
+    if (n > 0 && ni.L > 1 && !saved) return fail(HRKAN_ERR_INVALID_ARG, "saved is NULL");
+    const WsLayout L = layout(ni, n, 0);
+    TRY(check_ws(ws, ws_bytes, L.total));
+    char *w = (char *)ws;
+    if (ni.dtype == HRKAN_F64) {
+        RevSet<double> s{ch, (const double *)x, n, (const double *)seed, (const double *)saved,
+                         (double *)(w + L.bars0), (double *)(w + L.bars1)};
+        return reverse_impl<double>(ni, (const double *const *)W, &s, 1, (double *const *)gW_out,
+                                    accumulate, (double *)(w + L.part), stream);
+    }
+    if (ni.dtype == HRKAN_BF16)
+        return bf16_backward(ni, ch, W, (const float *)x, n, (const float *)seed,
+                             (const float *)saved, (float *const *)gW_out, accumulate, ws, ws_bytes,
+                             stream);
+    RevSet<float> s{ch, (const float *)x, n, (const float *)seed, (const float *)saved,
+                    (float *)(w + L.bars0), (float *)(w + L.bars1)};
+    return reverse_impl<float>(ni, (const float *const *)W, &s, 1, (float *const *)gW_out, accumulate,
+                               (float *)(w + L.part), stream);
+}
+
+int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
+               const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
+               size_t ws_bytes, hipStream_t stream)
+{
+    NetInfo ni;
+    TRY(check_net(net, &ni));
+    TRY(check_pde(pde));
+    TRY(check_weights(ni, W, "W"));
+    TRY(check_weights(ni, (const void *const *)gW_out, "gW_out"));
+    if (!pts) return fail(HRKAN_ERR_INVALID_ARG, "pts is NULL");
+    if (pts->n_int < 0 || pts->n_bc < 0) return fail(HRKAN_ERR_INVALID_ARG, "negative point count");
+    if (pts->n_int > 0 && !pts->x_int) return fail(HRKAN_ERR_INVALID_ARG, "x_int is NULL");
+    if (pts->n_bc > 0 && (!pts->x_bc || !pts->g_bc)) return fail(HRKAN_ERR_INVALID_ARG, "x_bc or g_bc is NULL");
+    if (!loss_out) return fail(HRKAN_ERR_INVALID_ARG, "loss_out is NULL");
+    for (const void *p : {pts->x_int, pts->x_bc, pts->g_bc})
+        if (p && !aligned(p, ni.elem)) return fail(HRKAN_ERR_INVALID_ARG, "point array misaligned");
+    size_t need = 0;
+    TRY(hrkan_workspace_bytes(net, pde, pts->n_int, pts->n_bc, &need));
+    TRY(check_ws(ws, ws_bytes, need));
+    if (ni.dtype == HRKAN_BF16) return bf16_step(ni, pde, W, pts, loss_out, gW_out, ws, ws_bytes, stream);
+    const WsLayout L = layout(ni, pts->n_int, pts->n_bc);
+    char *w = (char *)ws;
+    ChanCfg chi, chb;
+    TRY(mask_cfg(pde_mask(pde->kind), &chi));
+    TRY(mask_cfg(HRKAN_MASK_VALUE, &chb));
+    const int64_t ni_ = pts->n_int, nb_ = pts->n_bc;
+    const PdeParams pp{pde->kind, pde->nu, pde->alpha, pde->adv};
+
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        T *sv_int = (T *)(w + L.sv_int), *jets = (T *)(w + L.jets_int);
+        T *sv_bc = (T *)(w + L.sv_bc), *ubc = (T *)(w + L.ubc);
+        T *seed_int = (T *)(w + L.seed_int), *seed_bc = (T *)(w + L.seed_bc);
+        if (ni_ > 0)
+            TRY(forward_impl<T>(ni, chi, (const T *const *)W, (const T *)pts->x_int, ni_, jets, sv_int,
+                                nullptr, nullptr, stream));
+        if (nb_ > 0)
+            TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
+                                nullptr, nullptr, stream));
+        double *partials = (double *)(w + L.loss_part);
+        hipError_t e;
+        {
+            ProfScope ps("residual", -1, stream);
+            e = launch_residual<T>(pp, chi.C(), jets, (const T *)pts->x_int, ni_, ubc,
+                                   (const T *)pts->g_bc, nb_, nullptr, seed_int, seed_bc, partials,
+                                   L.nres, stream);
+        }
+        if (e != hipSuccess) return hip_fail(e, "residual launch");
+        {
+            ProfScope ps("loss", -1, stream);
+            e = launch_loss_final(partials, L.nres, ni_, nb_, pde->alpha, loss_out, (uint32_t *)w,
+                                  stream);
+        }
+        if (e != hipSuccess) return hip_fail(e, "loss launch");
+        RevSet<T> sets[2] = {
+            {chi, (const T *)pts->x_int, ni_, seed_int, sv_int, (T *)(w + L.bars0), (T *)(w + L.bars1)},
+            {chb, (const T *)pts->x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
+        };
+        return reverse_impl<T>(ni, (const T *const *)W, sets, 2, (T *const *)gW_out, 0,
+                               (T *)(w + L.part), stream);
+    };
+    if (ni.dtype == HRKAN_F64) return run(double{});
+    return run(float{});
+}
+
+int hrkan_read_status(void *ws, size_t ws_bytes, hipStream_t stream, uint32_t *flags)
+{
+    if (!flags) return fail(HRKAN_ERR_INVALID_ARG, "flags is NULL");
+    TRY(check_ws(ws, ws_bytes, 256));
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, ws, sizeof v, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ws, 0, sizeof v, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "status read");
+    *flags = v;
+    return HRKAN_OK;
+}
+
+}  // extern "C"

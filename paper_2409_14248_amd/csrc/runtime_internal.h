@@ -1,0 +1,70 @@
+// runtime_internal.h -- host-side helpers shared by the runtime sources.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hrkan.h"
+#include "internal.h"
+
+namespace hrk {
+
+// Validated copy of a network description.
+struct NetInfo {
+    int L;
+    int w[HRKAN_MAX_LAYERS + 1];
+    int G, k, m, nb;
+    double lo, hi;
+    int dtype;
+    int S;           // BF16 product terms
+    size_t elem;     // bytes of one array element (8 for F64, else 4)
+    int maxw;
+    int64_t n_params;
+};
+
+// Byte offsets of the workspace regions.
+struct WsLayout {
+    size_t status, loss_part, sv_int, jets_int, sv_bc, ubc, seed_int, seed_bc;
+    size_t bars0, bars1, bbars0, bbars1, part;
+    int64_t part_elems;
+    int nres;
+    size_t total;
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int check_net(const hrkan_net_desc *d, NetInfo *ni);
+int mask_cfg(uint32_t mask, ChanCfg *ch);
+template <typename T> GridP<T> make_grid(const NetInfo &ni);
+int64_t saved_elems(const NetInfo &ni, int C, int64_t n);
+int dw_splits(const NetInfo &ni, int l, int64_t n);
+WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc);
+
+// Brackets one kernel launch with HIP events while profiling is enabled.
+class ProfScope {
+  public:
+    ProfScope(const char *name, int layer, hipStream_t st);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    hipStream_t st_;
+    int idx_;
+};
+bool prof_on();
+
+// Workspace beyond `layout` needed by the BF16 path (packed weights).
+size_t extra_ws_bytes(const NetInfo &ni, int64_t n_int, int64_t n_bc);
+
+// BF16 path (matrix-core contractions, FP32 jets).
+int bf16_forward(const NetInfo &ni, ChanCfg ch, const void *const *W, const float *x, int64_t n,
+                 float *jets_out, float *saved, void *ws, size_t ws_bytes, hipStream_t st);
+int bf16_backward(const NetInfo &ni, ChanCfg ch, const void *const *W, const float *x, int64_t n,
+                  const float *seed, const float *saved, float *const *gW, int accumulate, void *ws,
+                  size_t ws_bytes, hipStream_t st);
+int bf16_step(const NetInfo &ni, const hrkan_pde_desc *pde, const void *const *W,
+              const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
+              size_t ws_bytes, hipStream_t st);
+
+}  // namespace hrk

@@ -100,6 +100,8 @@ class Workload:
 
 
 def _cell_centred(lo: float, hi: float, n: int) -> np.ndarray:
+    if n <= 0:
+        return np.zeros(0)
     return lo + (np.arange(n, dtype=np.float64) + 0.5) * ((hi - lo) / n)
 
 

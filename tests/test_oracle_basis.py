@@ -179,3 +179,31 @@ def test_golden_supports_fixture():
     s, e = O.supports(net)
     assert len(s) == g["n_basis"]
     assert np.allclose(s, g["s"], atol=1e-15) and np.allclose(e, g["e"], atol=1e-15)
+
+
+def test_rounding_model_matches_torch_roundings():
+    # The oracle's optional rounding model (used only to size FP32/BF16 error
+    # floors): a [2,1] net whose weight selects one basis function returns
+    # that feature rounded; compare with torch's float32 / bfloat16 casts
+    # (round to nearest even).
+    import torch
+    net = Net((2, 1), G=5)
+    s, e = O.supports(net)
+    W = np.zeros((16, 1))
+    W[4, 0] = 1.0
+    x = np.stack([np.linspace(-0.95, 0.95, 301), np.zeros(301)], 1)
+    exact = np.array([O.basis(4, s[4], e[4], v, 0)[0] for v in x[:, 0]])
+    for mode, split in (("f32", 1), ("bf16", 1), ("bf16", 2)):
+        with O.rounding(mode, split):
+            got = O.forward(net, [W], x)[0]
+        f32 = torch.tensor(exact, dtype=torch.float32)
+        if mode == "f32":
+            ref = f32.double()
+        else:
+            hi = f32.to(torch.bfloat16).float()
+            ref = hi.double()
+            if split == 2:
+                ref = ref + (f32 - hi).to(torch.bfloat16).double()
+            ref = ref.float().double()     # stored layer output in FP32
+        assert np.array_equal(got, ref.numpy()), mode
+    assert np.array_equal(O.forward(net, [W], x)[0], exact)   # model is off again
