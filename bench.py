@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--bf16-split", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every kernel from the host instead of replaying a HIP graph")
     return ap.parse_args()
 
 
@@ -80,17 +82,26 @@ def main():
     step = H.Step(pr, dtype, args.bf16_split)
     torch.cuda.synchronize()
 
+    def timed(fn, k):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(k):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / k
+
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
+    eager_ms = timed(step, args.steps)
+    ms = eager_ms
+    if not args.eager:
+        step.capture()
+        for _ in range(args.warmup):
+            step.replay()
+        ms = timed(step.replay, args.steps)
     loss = step.loss.cpu().numpy()
 
     # per-kernel times over a second timed pass (events around every launch)
@@ -161,6 +172,8 @@ def main():
             "n_int": pr.n_int, "n_bc": pr.n_bc,
             **({"bf16_split": args.bf16_split} if dtype == "bf16" else {}),
         },
+        "launch": "eager" if args.eager else "hip_graph",
+        "eager_ms_per_step": round(eager_ms, 5),
         "total_points_per_s": round((pr.n_int + pr.n_bc) / (ms * 1e-3), 1),
         "step_dense_tflops": round(step_flops / (ms * 1e-3) / 1e12, 3),
         "loss": [float(v) for v in loss],

@@ -41,8 +41,8 @@
  *     a channel mask, in the order U, X, XX, Y, YY (X = d/dx0, Y = d/dx1,
  *     where x1 is y for Poisson and t for Burgers).
  *   - Weights of layer l are [w_l * n_b][w_{l+1}] row-major, row i*n_b + b for
- *     input feature i and basis function b. Weight gradients use the same
- *     layout and the array type.
+ *     input feature i and basis function b, 16-byte aligned. Weight gradients
+ *     use the same layout, alignment and array type.
  */
 #ifndef HRKAN_H
 #define HRKAN_H

@@ -75,7 +75,9 @@ __device__ __forceinline__ int interval_of(const GridP<T> &g, T zeta)
 //        = -12 * inv_w^3 * d                                      (m == 2)
 // This is c_m (e-z)^m (z-s)^m of Eq. 2 differentiated through t(z), written in
 // the scaled variables; zero outside the open support.
-template <typename T, int ND>
+// MC > 0 fixes the order at compile time (no power loops); MC = 0 reads it
+// from the grid.
+template <typename T, int ND, int MC = 0>
 __device__ __forceinline__ void hr_bump(const GridP<T> &g, T zeta, int b, T *v)
 {
     const T a = zeta - T(b - g.k) * g.kappa;
@@ -83,7 +85,7 @@ __device__ __forceinline__ void hr_bump(const GridP<T> &g, T zeta, int b, T *v)
     const bool in = (a > T(0)) && (be > T(0)) && b >= 0 && b < g.nb;
     const T t = a * be;
     const T d = be - a;
-    const int m = g.m;
+    const int m = MC > 0 ? MC : g.m;
     const T tm2 = ipow(t, m - 2);
     const T fm = T(m);
     T v0 = tm2 * t * t;

@@ -381,18 +381,30 @@ hipError_t launch_dw_generic(ChanCfg ch, bool first, const T *zin, const T *ybar
 }
 
 // ---------------------------------------------------------------------------
-// out[e] (+)= sum over slices, slice order fixed, accumulated in double
+// out[e] (+)= sum over slices. A block takes 32 elements; its 8 slice lanes
+// each sum a fixed residue class of slices in double, then one thread adds
+// the 8 lane sums in order: a fixed summation order for every element.
 // ---------------------------------------------------------------------------
+constexpr int RD_EB = 32, RD_SL = NT / RD_EB;
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_reduce_splits(const T *__restrict__ part, int nsplit,
                                                       int64_t count, T *__restrict__ out,
                                                       int accumulate)
 {
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (e >= count) return;
-    double s = accumulate ? (double)out[e] : 0.0;
-    for (int k = 0; k < nsplit; ++k) s += (double)part[(int64_t)k * count + e];
-    out[e] = (T)s;
+    __shared__ double sh[RD_SL][RD_EB];
+    const int el = threadIdx.x % RD_EB, sl = threadIdx.x / RD_EB;
+    const int64_t e = (int64_t)blockIdx.x * RD_EB + el;
+    double s = 0.0;
+    if (e < count)
+        for (int k = sl; k < nsplit; k += RD_SL) s += (double)part[(int64_t)k * count + e];
+    sh[sl][el] = s;
+    __syncthreads();
+    if (sl == 0 && e < count) {
+        double t = accumulate ? (double)out[e] : 0.0;
+        for (int k = 0; k < RD_SL; ++k) t += sh[k][el];
+        out[e] = (T)t;
+    }
 }
 
 template <typename T>
@@ -400,8 +412,8 @@ hipError_t launch_reduce_splits(const T *part, int nsplit, int64_t count, T *out
                                 hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    k_reduce_splits<T><<<(unsigned)((count + NT - 1) / NT), NT, 0, st>>>(part, nsplit, count, out,
-                                                                          accumulate);
+    k_reduce_splits<T><<<(unsigned)((count + RD_EB - 1) / RD_EB), NT, 0, st>>>(part, nsplit, count, out,
+                                                                               accumulate);
     return hipGetLastError();
 }
 

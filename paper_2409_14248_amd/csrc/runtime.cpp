@@ -8,9 +8,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "hrkan.h"
 #include "internal.h"
+#include "kernels_bs.h"
 #include "runtime_internal.h"
 
 namespace hrk {
@@ -120,10 +122,32 @@ int64_t saved_elems(const NetInfo &ni, int C, int64_t n)
 }
 
 // Slices of the weight-gradient reduction for n points at layer l.
+// The FP32 and BF16 arrays go through the matrix-core kernels where the
+// layer shape allows it; FP64 (and other shapes) through the generic ones.
+bool use_bs32(const NetInfo &ni, int l)
+{
+    return ni.dtype != HRKAN_F64 && ni.m == 4 && ni.k == 3 &&
+           bs32_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb});
+}
+
 int dw_splits(const NetInfo &ni, int l, int64_t n)
 {
     if (n <= 0) return 0;
-    return dw_generic_splits(n, LayerShape{ni.w[l], ni.w[l + 1], ni.nb});
+    const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
+    return use_bs32(ni, l) ? dw_bs32_splits(n, ls) : dw_generic_splits(n, ls);
+}
+
+int cu_blocks()
+{
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached = 2 * cus;
+    }
+    return cached;
 }
 
 static int64_t max_part_elems(const NetInfo &ni, int64_t n_a, int64_t n_b)
@@ -193,8 +217,15 @@ int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, i
         hipError_t e;
         {
             ProfScope ps("fwd", l, st);
-            e = launch_fwd_generic<T>(ch, l == 0, zin, W[l], zout, n,
-                                      LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, g, st);
+            const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
+            if constexpr (std::is_same<T, float>::value) {
+                if (use_bs32(ni, l))
+                    e = launch_fwd_bs32(ch, l == 0, zin, W[l], zout, n, ls, g, cu_blocks(), st);
+                else
+                    e = launch_fwd_generic<T>(ch, l == 0, zin, W[l], zout, n, ls, g, st);
+            } else {
+                e = launch_fwd_generic<T>(ch, l == 0, zin, W[l], zout, n, ls, g, st);
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "forward layer launch");
         zin = zout;
@@ -245,8 +276,15 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
             hipError_t e;
             {
                 ProfScope ps("dw", l, st);
-                e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar[s], part + (int64_t)tot * kn, ns, S.n,
-                                         ls, g, st);
+                T *dst = part + (int64_t)tot * kn;
+                if constexpr (std::is_same<T, float>::value) {
+                    if (use_bs32(ni, l))
+                        e = launch_dw_bs32(S.ch, l == 0, zin, ybar[s], dst, ns, S.n, ls, g, st);
+                    else
+                        e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar[s], dst, ns, S.n, ls, g, st);
+                } else {
+                    e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar[s], dst, ns, S.n, ls, g, st);
+                }
             }
             if (e != hipSuccess) return hip_fail(e, "weight-gradient launch");
             tot += ns;
@@ -270,7 +308,14 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
             hipError_t e;
             {
                 ProfScope ps("dx", l, st);
-                e = launch_dx_generic<T>(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, st);
+                if constexpr (std::is_same<T, float>::value) {
+                    if (use_bs32(ni, l))
+                        e = launch_dx_bs32(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, cu_blocks(), st);
+                    else
+                        e = launch_dx_generic<T>(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, st);
+                } else {
+                    e = launch_dx_generic<T>(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, st);
+                }
             }
             if (e != hipSuccess) return hip_fail(e, "input-bar launch");
             ybar[s] = zbar;
@@ -293,7 +338,7 @@ int check_weights(const NetInfo &ni, const void *const *W, const char *what)
     if (!W) return fail(HRKAN_ERR_INVALID_ARG, "%s array is NULL", what);
     for (int l = 0; l < ni.L; ++l) {
         if (!W[l]) return fail(HRKAN_ERR_INVALID_ARG, "%s[%d] is NULL", what, l);
-        if (!aligned(W[l], ni.elem)) return fail(HRKAN_ERR_INVALID_ARG, "%s[%d] misaligned", what, l);
+        if (!aligned(W[l], 16)) return fail(HRKAN_ERR_INVALID_ARG, "%s[%d] is not 16-byte aligned", what, l);
     }
     return HRKAN_OK;
 }

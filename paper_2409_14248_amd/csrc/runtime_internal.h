@@ -38,6 +38,8 @@ int mask_cfg(uint32_t mask, ChanCfg *ch);
 template <typename T> GridP<T> make_grid(const NetInfo &ni);
 int64_t saved_elems(const NetInfo &ni, int C, int64_t n);
 int dw_splits(const NetInfo &ni, int l, int64_t n);
+bool use_bs32(const NetInfo &ni, int l);
+int cu_blocks();
 WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc);
 
 // Brackets one kernel launch with HIP events while profiling is enabled.

@@ -323,6 +323,26 @@ class Step:
         return step(self.nd, self.pd, self.W, self.x_int, self.x_bc, self.g_bc, self.ws,
                     self.loss, self.gW, stream)
 
+    def capture(self) -> "torch.cuda.CUDAGraph":
+        """Record one step into a HIP graph (same kernels, same buffers);
+        replay() then re-runs the step with a single graph launch."""
+        self()                                    # eager first run: one-time kernel setup
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self()
+        torch.cuda.synchronize()
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+        return self.loss, self.gW
+
 
 # ---------------------------------------------------------------------------
 # autograd
