@@ -1,4 +1,5 @@
-// kernels_bs32.hip -- FP32 matrix-core kernels of one KAN layer.
+// kernels_bs32.hip -- FP32 matrix-core kernels of one KAN layer for the
+// paper's HR basis with k = 3 supports and order m = 4.
 //
 // Forward and input-bar contractions use the 16-block 4x4x1 FP32 MFMA with
 // ONE COLLOCATION POINT PER BLOCK: the block's 4 rows are the point's jet
@@ -12,10 +13,14 @@
 // point p0 + b; s = lane & 3 is the block row (channel) for the A operand and
 // the block column for the B operand and the result.
 //
-// The weight gradient is a dense 32x32x2 FP32 MFMA GEMM over points:
-// gW[K x N] = A^T [K x (points*C)] * Ybar [(points*C) x N], with the A
-// operand assembled from LDS-staged live features (zeros elsewhere).
+// Window: in the scaled coordinate zt (supports of width 2, knots at
+// multiples of 0.5) a point in interval q = floor(2 zt) has live functions
+// q..q+3 clipped to 0..nb-1. Every kernel uses the 4-row window
+// qa..qa+3 with qa = clamp(q, 0, nb-4), which holds all live functions, and
+// evaluates each window row's bump directly (zero off its support), so row
+// addresses are fixed offsets from one base and no lane needs a select.
 #include <algorithm>
+#include <cstdlib>
 
 #include "internal.h"
 #include "kernels_bs.h"
@@ -23,12 +28,17 @@
 namespace hrk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef float f16v __attribute__((ext_vector_type(16)));
 
-constexpr int NT = 256;                 // threads per block (4 waves)
+constexpr int NT = 256;                 // threads of the 4-wave kernels
+constexpr int NT8 = 512;                // threads of the 8-wave kernels
 constexpr int PW = 16;                  // points per wave
-constexpr int PB = 4 * PW;              // points per block
-constexpr int LDS_W_BYTES = 112 * 1024; // weight staging budget
+constexpr int TP = 8 * PW;              // points per tile of an 8-wave block
+constexpr int KJ = 4;                   // inputs per staged jet chunk
+constexpr int LDS_FWD = 78 * 1024;      // per 8-wave block: two blocks per CU
+
+// Waves per SIMD the 8-wave kernels are compiled for: two blocks per CU
+// (registers <= 128) when a point's channels fit one 4-row group.
+template <int O0, int O1> constexpr int fwd_waves() { return Ch<O0, O1>::C <= 4 ? 4 : 2; }
 
 // Broadcast lane T of each quad (DPP quad_perm [T,T,T,T]).
 template <int T>
@@ -45,63 +55,71 @@ __device__ __forceinline__ float quad_sum(float v)
     return v;
 }
 
-// Coefficients (of v, v', v'') of the feature of channel c:
-//   U: v   X: v' zx   XX: v'' zx^2 + v' zxx   Y: v' zy   YY: v'' zy^2 + v' zyy
+// Window start clamp(floor(2 zt), 0, nb - 4); a NaN coordinate gives 0 so
+// that the bumps evaluated there carry the NaN. Needs nb >= 4.
+__device__ __forceinline__ int window_k3(float zt, int nb)
+{
+    return (int)fminf(fmaxf(2.f * zt, 0.f), (float)(nb - 4));
+}
+
+// Bump b (k = 3, m = 4) at scaled coordinate zt, derivatives up to ND (in
+// the unscaled coordinate): a = zt - (b-3)/2 and be = 2 - a are the
+// distances to the support ends; with t = a be and d = be - a,
+//   v = t^4, v' = 4 w t^3 d, v'' = 4 w^2 t^2 (3 d^2 - 2 t),
+//   v''' = 24 w^3 t d (d^2 - 3 t),   w = inv_w,
+// and zero off the open support (a NaN coordinate propagates).
+template <int ND>
+__device__ __forceinline__ void bump_k3m4(float zt, int b, float inv_w, float *v)
+{
+    const float a = zt - 0.5f * (float)b + 1.5f;
+    const float be = 2.f - a;
+    const bool in = !(a <= 0.f) && !(be <= 0.f);
+    const float t = a * be, d = be - a, t2 = t * t;
+    v[0] = in ? t2 * t2 : 0.f;
+    v[1] = in ? (4.f * inv_w) * (t2 * t) * d : 0.f;
+    if constexpr (ND >= 2) v[2] = in ? (4.f * inv_w * inv_w) * t2 * (3.f * d * d - 2.f * t) : 0.f;
+    if constexpr (ND >= 3) v[3] = in ? (24.f * inv_w * inv_w * inv_w) * t * d * (d * d - 3.f * t) : 0.f;
+}
+
+// Feature of channel c as a0 v + a1 v' + a2 v'' (the chain rule of the jets):
+//   U: (1, -, -)  X: (0, X, -)  XX: (0, XX, X^2)  Y: (0, Y, -)  YY: (0, YY, Y^2)
+// src1 / src2 are the jet channels that give a1 and sqrt(a2); C (one past the
+// last channel) names a staged zero row.
 template <int O0, int O1>
-__device__ __forceinline__ void channel_coeffs(int c, const float *zj, float &a0, float &a1, float &a2)
+__device__ __forceinline__ void channel_sources(int c, float &a0, int &src1, int &src2)
 {
     using CH = Ch<O0, O1>;
-    a0 = 0.f; a1 = 0.f; a2 = 0.f;
-    if (c == CH::U) a0 = 1.f;
-    if constexpr (CH::X >= 0) if (c == CH::X) a1 = zj[CH::X];
-    if constexpr (CH::XX >= 0) if (c == CH::XX) { a1 = zj[CH::XX]; a2 = zj[CH::X] * zj[CH::X]; }
-    if constexpr (CH::Y >= 0) if (c == CH::Y) a1 = zj[CH::Y];
-    if constexpr (CH::YY >= 0) if (c == CH::YY) { a1 = zj[CH::YY]; a2 = zj[CH::Y] * zj[CH::Y]; }
+    constexpr int C = CH::C;
+    a0 = (c == CH::U) ? 1.f : 0.f;
+    src1 = C;
+    src2 = C;
+    if (c == CH::X || c == CH::XX || c == CH::Y || c == CH::YY) src1 = c;
+    if (CH::XX >= 0 && c == CH::XX) src2 = CH::X;
+    if (CH::YY >= 0 && c == CH::YY) src2 = CH::Y;
 }
 
-template <typename T, int O0, int O1, bool FIRST>
-__device__ __forceinline__ void load_jets_guarded(const T *__restrict__ zin, int64_t n, int win,
-                                                  int i, int64_t p, bool ok, T *zj)
-{
-    constexpr int C = Ch<O0, O1>::C;
-    if (!ok) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) zj[c] = T(0);
-        return;
-    }
-    if constexpr (FIRST) {
-        input_jets<T, O0, O1>(zin, p, i, zj);
-    } else {
-#pragma unroll
-        for (int c = 0; c < C; ++c) zj[c] = zin[((int64_t)c * win + i) * n + p];
-    }
-}
-
-// Stage weight rows [r0, r0 + nrows) x N into LDS with row stride NS.
+// Stage weight rows [r0, r0 + nrows) (N floats each) into LDS, row stride NS.
+template <int BLK>
 __device__ __forceinline__ void stage_rows(float *sW, const float *__restrict__ W, int r0, int nrows,
                                            int N, int NS)
 {
     const int n4 = N / 4;
-    for (int e = threadIdx.x; e < nrows * n4; e += NT) {
+    for (int e = threadIdx.x; e < nrows * n4; e += BLK) {
         const int r = e / n4, c4 = e % n4;
-        const f4 v = *reinterpret_cast<const f4 *>(W + (size_t)(r0 + r) * N + 4 * c4);
-        *reinterpret_cast<f4 *>(sW + r * NS + 4 * c4) = v;
+        *reinterpret_cast<f4 *>(sW + r * NS + 4 * c4) =
+            *reinterpret_cast<const f4 *>(W + (size_t)(r0 + r) * N + 4 * c4);
     }
 }
 
-// ---------------------------------------------------------------------------
-// Staging of input jets. A tile is PB = 64 points; its inputs are taken in
-// chunks of KJ. A chunk's jets are loaded from HBM into registers one chunk
-// ahead (all loads of a chunk in flight together) and written to LDS as
-// [input][channel][point] while the previous chunk is being computed.
-// ---------------------------------------------------------------------------
-constexpr int KJ = 8;
-
-template <int O0, int O1, bool FIRST>
+// A chunk of KJ inputs' jets for a tile of TP points, prefetched into
+// registers one chunk ahead and stored to LDS as [input][channel][point] with
+// C + 1 channel rows per input (the last one stays zero).
+template <int O0, int O1, bool FIRST, int BLK>
 struct JetChunk {
     static constexpr int C = Ch<O0, O1>::C;
-    static constexpr int E = KJ * C * PB;            // elements per chunk
-    static constexpr int R = (E + NT - 1) / NT;      // registers per thread
+    static constexpr int CS = (C + 1) * TP;     // floats per staged input
+    static constexpr int E = KJ * C * TP;
+    static constexpr int R = (E + BLK - 1) / BLK;
     float r[R];
 
     __device__ __forceinline__ void load(const float *__restrict__ zin, int64_t n, int win,
@@ -109,59 +127,80 @@ struct JetChunk {
     {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int e = threadIdx.x + k * NT;
-            const int pp = e % PB, rest = e / PB, c = rest % C, il = rest / C;
+            const int e = threadIdx.x + k * BLK;
+            const int pp = e % TP, rest = e / TP, c = rest % C, il = rest / C;
             const int i = jc * KJ + il;
-            const int64_t p = tile * PB + pp;
-            float v = 0.f;
-            if (e < E && i < win && p < n) {
-                if constexpr (FIRST) {
-                    float zj[C];
-                    input_jets<float, O0, O1>(zin, p, i, zj);
-                    v = zj[c];
-                } else {
-                    v = zin[((int64_t)c * win + i) * n + p];
-                }
+            const int64_t p = tile * TP + pp;
+            const bool ok = e < E && i < win && p < n;
+            const int ic = ok ? i : 0;
+            const int64_t pc = ok ? p : 0;
+            float v;
+            if constexpr (FIRST) {
+                float zj[C];
+                input_jets<float, O0, O1>(zin, pc, ic, zj);
+                v = zj[c];
+            } else {
+                v = zin[(int64_t)(c * win + ic) * n + pc];
             }
-            r[k] = v;
+            r[k] = ok ? v : 0.f;
         }
     }
     __device__ __forceinline__ void store(float *sZ) const
     {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int e = threadIdx.x + k * NT;
-            if (e < E) sZ[e] = r[k];
+            const int e = threadIdx.x + k * BLK;
+            if (e < E) sZ[e + (e / (C * TP)) * TP] = r[k];
         }
+    }
+    __device__ __forceinline__ static void zero_rows(float *sZ)
+    {
+        for (int e = threadIdx.x; e < KJ * TP; e += BLK) sZ[(e / TP) * CS + C * TP + e % TP] = 0.f;
     }
 };
 
 // ---------------------------------------------------------------------------
-// forward: zout[c][j][p] = sum_i sum_t W[i*nb + q + t][j] * A_c(p, i, t)
-// Persistent blocks walk tiles of 64 points (16 per wave). NQ = N/4 output
-// chunks; block column s owns outputs j = s*NQ + k, k < NQ.
+// forward: zout[c][j][p] = sum_i sum_t W[i*nb + qa + t][j] * A_c(p, i, t)
+// Persistent 8-wave blocks walk tiles of 128 points (16 per wave); the
+// block's weight rows are staged once when they fit (KI >= win), else per
+// chunk of KI inputs. NQ = N/4; block column s owns outputs j = s*NQ + k.
 // ---------------------------------------------------------------------------
 template <int O0, int O1, bool FIRST, int NQ>
-__global__ __launch_bounds__(NT) void k_fwd_bs(const float *__restrict__ zin,
-                                               const float *__restrict__ W,
-                                               float *__restrict__ zout, int64_t n, int win,
-                                               int KI, GridP<float> g)
+__global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_fwd_bs(const float *__restrict__ zin,
+                                                   const float *__restrict__ W,
+                                                   float *__restrict__ zout, int64_t n, int win,
+                                                   int KI, GridP<float> g)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int RG = (C + 3) / 4;
     constexpr int N = 4 * NQ;
     constexpr int NS = N + 4;
-    using JCk = JetChunk<O0, O1, FIRST>;
-    extern __shared__ float smem[];
+    using JCk = JetChunk<O0, O1, FIRST, NT8>;
+    constexpr int CS = JCk::CS;
+    extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     float *sW = smem;
     float *sZ = smem + KI * nb * NS;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int bl = lane >> 2, s = lane & 3;
-    const int64_t ntiles = (n + PB - 1) / PB;
+    const int pt = wv * PW + bl;
+    const int64_t ntiles = (n + TP - 1) / TP;
     const int njc = (win + KJ - 1) / KJ;
     const bool single = KI >= win;
-    if (single) stage_rows(sW, W, 0, win * nb, N, NS);
+    JCk::zero_rows(sZ);
+    if (single) stage_rows<NT8>(sW, W, 0, win * nb, N, NS);
+
+    // this lane's channel rows: coefficient sources (offsets in a staged input)
+    float a0[RG];
+    int off1[RG], off2[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        int s1, s2;
+        channel_sources<O0, O1>(4 * r + s, a0[r], s1, s2);
+        off1[r] = s1 * TP + pt;
+        off2[r] = s2 * TP + pt;
+    }
 
     JCk pre;
     int64_t tile = blockIdx.x;
@@ -175,13 +214,12 @@ __global__ __launch_bounds__(NT) void k_fwd_bs(const float *__restrict__ zin,
 #pragma unroll
                 for (int k = 0; k < NQ; ++k) acc[r][k] = (f4){0.f, 0.f, 0.f, 0.f};
         }
-        const int ib = jc * KJ;                         // first input of this chunk
-        const int iW = single ? 0 : (ib / KI) * KI;     // first input of the staged W rows
+        const int ib = jc * KJ;
+        const int iW = single ? 0 : (ib / KI) * KI;
         __syncthreads();
         pre.store(sZ);
-        if (!single && ib % KI == 0) stage_rows(sW, W, iW * nb, (min(win, iW + KI) - iW) * nb, N, NS);
+        if (!single && ib % KI == 0) stage_rows<NT8>(sW, W, iW * nb, min(KI, win - iW) * nb, N, NS);
         __syncthreads();
-        // prefetch the next chunk (next inputs of this tile, or the next tile)
         const int64_t cur_tile = tile;
         if (++jc == njc) {
             jc = 0;
@@ -189,40 +227,36 @@ __global__ __launch_bounds__(NT) void k_fwd_bs(const float *__restrict__ zin,
         }
         if (tile < ntiles) pre.load(zin, n, win, tile, jc);
 
-        const int64_t p = cur_tile * PB + wv * PW + bl;
         const int ie = min(win, ib + KJ);
         for (int i = ib; i < ie; ++i) {
-            const float *zp = sZ + ((i - ib) * C) * PB + wv * PW + bl;
-            float zj[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) zj[c] = zp[c * PB];
-            const float zt = zeta_of(g, zj[0]);
-            const int q = interval_of(g, zt);
-            // this lane evaluates live function t = s; the quad shares it
+            const float *zc = sZ + (i - ib) * CS;
+            const float zt = zc[pt] * inv_w + zoff;
+            const int qa = window_k3(zt, nb);
             float v[3];
-            hr_bump<float, 2, 4>(g, zt, q + s, v);
-            float a0[RG], a1[RG], a2[RG];
-#pragma unroll
-            for (int r = 0; r < RG; ++r) channel_coeffs<O0, O1>(4 * r + s, zj, a0[r], a1[r], a2[r]);
+            bump_k3m4<2>(zt, qa + s, inv_w, v);        // this lane: window row t = s
             float vt[4][3];
             vt[0][0] = qbcast<0>(v[0]); vt[0][1] = qbcast<0>(v[1]); vt[0][2] = qbcast<0>(v[2]);
             vt[1][0] = qbcast<1>(v[0]); vt[1][1] = qbcast<1>(v[1]); vt[1][2] = qbcast<1>(v[2]);
             vt[2][0] = qbcast<2>(v[0]); vt[2][1] = qbcast<2>(v[1]); vt[2][2] = qbcast<2>(v[2]);
             vt[3][0] = qbcast<3>(v[0]); vt[3][1] = qbcast<3>(v[1]); vt[3][2] = qbcast<3>(v[2]);
+            float a1[RG], a2[RG];
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                a1[r] = zc[off1[r]];
+                const float x2 = zc[off2[r]];
+                a2[r] = x2 * x2;
+            }
+            const float *wr = sW + ((i - iW) * nb + qa) * NS + s * NQ;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int b = q + t;
-                const bool live = b >= 0 && b < nb;
-                const int row = (i - iW) * nb + (live ? b : 0);
-                const float *wr = sW + row * NS + s * NQ;
                 float bw[NQ];
 #pragma unroll
                 for (int k4 = 0; k4 < NQ / 4; ++k4) {
-                    const f4 w4 = *reinterpret_cast<const f4 *>(wr + 4 * k4);
-                    bw[4 * k4 + 0] = live ? w4[0] : 0.f;
-                    bw[4 * k4 + 1] = live ? w4[1] : 0.f;
-                    bw[4 * k4 + 2] = live ? w4[2] : 0.f;
-                    bw[4 * k4 + 3] = live ? w4[3] : 0.f;
+                    const f4 w4 = *reinterpret_cast<const f4 *>(wr + t * NS + 4 * k4);
+                    bw[4 * k4 + 0] = w4[0];
+                    bw[4 * k4 + 1] = w4[1];
+                    bw[4 * k4 + 2] = w4[2];
+                    bw[4 * k4 + 3] = w4[3];
                 }
 #pragma unroll
                 for (int r = 0; r < RG; ++r) {
@@ -233,6 +267,7 @@ __global__ __launch_bounds__(NT) void k_fwd_bs(const float *__restrict__ zin,
                 }
             }
         }
+        const int64_t p = cur_tile * TP + pt;
         if (jc == 0 && p < n) {                 // the tile is complete
 #pragma unroll
             for (int r = 0; r < RG; ++r)
@@ -241,40 +276,43 @@ __global__ __launch_bounds__(NT) void k_fwd_bs(const float *__restrict__ zin,
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int c = 4 * r + e;
-                        if (c < C) zout[((int64_t)c * N + s * NQ + k) * n + p] = acc[r][k][e];
+                        if (c < C) zout[(int64_t)(c * N + s * NQ + k) * n + p] = acc[r][k][e];
                     }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// input bars: Ab_c(p,i,t) = sum_j W[i*nb + q + t][j] * ybar[c][j][p]; then the
-// adjoint of the features through v..v''' gives zbar[.][i][p].
-// Block row = channel, block column = live function t. Two inputs are in
-// flight at a time so consecutive MFMAs accumulate into different results.
+// input bars: Ab_c(p,i,t) = sum_j W[i*nb + qa + t][j] * ybar[c][j][p]; then
+// the adjoint of the features through v..v''' gives zbar[.][i][p].
+// Block row = channel, block column = window row t. Even and odd output
+// quads accumulate in separate chains so consecutive MFMAs are independent.
 // ---------------------------------------------------------------------------
 template <int O0, int O1, int NQ>
-__global__ __launch_bounds__(NT) void k_dx_bs(const float *__restrict__ zin,
-                                              const float *__restrict__ ybar,
-                                              const float *__restrict__ W,
-                                              float *__restrict__ zbar, int64_t n, int win, int KI,
-                                              GridP<float> g)
+__global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const float *__restrict__ zin,
+                                                  const float *__restrict__ ybar,
+                                                  const float *__restrict__ W,
+                                                  float *__restrict__ zbar, int64_t n, int win,
+                                                  int KI, GridP<float> g)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int RG = (C + 3) / 4;
     constexpr int N = 4 * NQ;
     constexpr int NS = N + 4;
-    using JCk = JetChunk<O0, O1, false>;
-    extern __shared__ float smem[];
+    using JCk = JetChunk<O0, O1, false, NT8>;
+    constexpr int CS = JCk::CS;
+    extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     float *sW = smem;
     float *sZ = smem + KI * nb * NS;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int bl = lane >> 2, s = lane & 3;
-    const int64_t ntiles = (n + PB - 1) / PB;
+    const int pt = wv * PW + bl;
+    const int64_t ntiles = (n + TP - 1) / TP;
     const int njc = (win + KJ - 1) / KJ;
     const bool single = KI >= win;
-    if (single) stage_rows(sW, W, 0, win * nb, N, NS);
+    if (single) stage_rows<NT8>(sW, W, 0, win * nb, N, NS);
 
     JCk pre;
     int64_t tile = blockIdx.x;
@@ -282,23 +320,27 @@ __global__ __launch_bounds__(NT) void k_dx_bs(const float *__restrict__ zin,
     if (tile < ntiles) pre.load(zin, n, win, tile, 0);
     float yb[RG][N];
     while (tile < ntiles) {
-        const int64_t p = tile * PB + wv * PW + bl;
+        const int64_t p = tile * TP + pt;
         const bool ok = p < n;
         if (jc == 0) {
             // the output bars of this lane's channel rows, all N outputs
+            const int64_t pc = ok ? p : 0;
 #pragma unroll
             for (int r = 0; r < RG; ++r) {
                 const int c = 4 * r + s;
+                const int cc = c < C ? c : 0;
 #pragma unroll
-                for (int j = 0; j < N; ++j)
-                    yb[r][j] = (ok && c < C) ? ybar[((int64_t)c * N + j) * n + p] : 0.f;
+                for (int j = 0; j < N; ++j) {
+                    const float y = ybar[(int64_t)(cc * N + j) * n + pc];
+                    yb[r][j] = (ok && c < C) ? y : 0.f;
+                }
             }
         }
         const int ib = jc * KJ;
         const int iW = single ? 0 : (ib / KI) * KI;
         __syncthreads();
         pre.store(sZ);
-        if (!single && ib % KI == 0) stage_rows(sW, W, iW * nb, (min(win, iW + KI) - iW) * nb, N, NS);
+        if (!single && ib % KI == 0) stage_rows<NT8>(sW, W, iW * nb, min(KI, win - iW) * nb, N, NS);
         __syncthreads();
         if (++jc == njc) {
             jc = 0;
@@ -307,70 +349,50 @@ __global__ __launch_bounds__(NT) void k_dx_bs(const float *__restrict__ zin,
         if (tile < ntiles) pre.load(zin, n, win, tile, jc);
 
         const int ie = min(win, ib + KJ);
-        for (int i = ib; i < ie; i += 2) {
-            const int npair = (i + 1 < ie) ? 2 : 1;
-            float zj[2][C], zt[2];
-            int q[2];
-            f4 ab[2][RG];
+        for (int i = ib; i < ie; ++i) {
+            const float *zc = sZ + (i - ib) * CS + pt;
+            float zj[C];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const float *zp = sZ + ((i + (u < npair ? u : 0) - ib) * C) * PB + wv * PW + bl;
+            for (int c = 0; c < C; ++c) zj[c] = zc[c * TP];
+            const float zt = zj[0] * inv_w + zoff;
+            const int qa = window_k3(zt, nb);
+            // this lane (column t = s) reads window row qa + s
+            const float *wr = sW + ((i - iW) * nb + qa + s) * NS;
+            f4 ab[2][RG];       // two accumulation chains: even / odd output quads
 #pragma unroll
-                for (int c = 0; c < C; ++c) zj[u][c] = (u < npair) ? zp[c * PB] : 0.f;
-                zt[u] = zeta_of(g, zj[u][0]);
-                q[u] = interval_of(g, zt[u]);
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int r = 0; r < RG; ++r) ab[u][r] = (f4){0.f, 0.f, 0.f, 0.f};
-            }
-            // this lane (column t = s) reads the weight row of function q + s
-            const float *wr[2];
-            bool live[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int b = q[u] + s;
-                live[u] = u < npair && b >= 0 && b < nb;
-                wr[u] = sW + ((i + (u < npair ? u : 0) - iW) * nb + (live[u] ? b : 0)) * NS;
-            }
+                for (int r = 0; r < RG; ++r) ab[h][r] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int j4 = 0; j4 < NQ; ++j4) {
-                f4 w4[2];
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    w4[u] = *reinterpret_cast<const f4 *>(wr[u] + 4 * j4);
-                    if (!live[u]) w4[u] = (f4){0.f, 0.f, 0.f, 0.f};
-                }
+                const f4 w4 = *reinterpret_cast<const f4 *>(wr + 4 * j4);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
-                    for (int u = 0; u < 2; ++u)
-#pragma unroll
-                        for (int r = 0; r < RG; ++r)
-                            ab[u][r] = __builtin_amdgcn_mfma_f32_4x4x1f32(yb[r][4 * j4 + e], w4[u][e],
-                                                                          ab[u][r], 0, 0, 0);
+                    for (int r = 0; r < RG; ++r)
+                        ab[j4 & 1][r] = __builtin_amdgcn_mfma_f32_4x4x1f32(yb[r][4 * j4 + e], w4[e],
+                                                                           ab[j4 & 1][r], 0, 0, 0);
             }
-            // lane (b, t): ab[u][r][e] = Abar of channel 4r+e for function t = s
+            // lane (block, t): ab[.][r][e] = Abar of channel 4r+e for row t = s
+            float v[4];
+            bump_k3m4<3>(zt, qa + s, inv_w, v);
+            float Ab[C];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                float v[4];
-                hr_bump<float, 3, 4>(g, zt[u], q[u] + s, v);
-                float Ab[C];
+            for (int c = 0; c < C; ++c) Ab[c] = ab[0][c / 4][c % 4] + ab[1][c / 4][c % 4];
+            float zb[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) Ab[c] = ab[u][c / 4][c % 4];
-                float zb[C];
+            for (int c = 0; c < C; ++c) zb[c] = 0.f;
+            features_adjoint<float, O0, O1>(v, zj, Ab, zb);
 #pragma unroll
-                for (int c = 0; c < C; ++c) zb[c] = 0.f;
-                features_adjoint<float, O0, O1>(v, zj[u], Ab, zb);
+            for (int c = 0; c < C; ++c) zb[c] = quad_sum(zb[c]);
+            if (ok) {
 #pragma unroll
-                for (int c = 0; c < C; ++c) zb[c] = quad_sum(zb[c]);
-                if (ok && u < npair) {
+                for (int r = 0; r < RG; ++r) {
+                    const int c = 4 * r + s;
+                    float val = zb[0];
 #pragma unroll
-                    for (int r = 0; r < RG; ++r) {
-                        const int c = 4 * r + s;
-                        float val = zb[0];
-#pragma unroll
-                        for (int cc = 1; cc < C; ++cc) val = (c == cc) ? zb[cc] : val;
-                        if (c < C) zbar[((int64_t)c * win + i + u) * n + p] = val;
-                    }
+                    for (int cc = 1; cc < C; ++cc) val = (c == cc) ? zb[cc] : val;
+                    if (c < C) zbar[(int64_t)(c * win + i) * n + p] = val;
                 }
             }
         }
@@ -379,55 +401,64 @@ __global__ __launch_bounds__(NT) void k_dx_bs(const float *__restrict__ zin,
 
 // ---------------------------------------------------------------------------
 // weight gradient, block-sparse:
-//   gW[i*nb + q + t][j] += sum_c A_c(p, i, t) * ybar[c][j][p]
+//   gW[i*nb + qa + t][j] += sum_c A_c(p, i, t) * ybar[c][j][p]
 // One 4x4x1 MFMA block is (input feature, chunk of 4 outputs) of ONE point:
-// rows = live function t, columns = 4 outputs, K = one jet channel (C MFMAs
+// rows = window row t, columns = 4 outputs, K = one jet channel (C MFMAs
 // accumulate the channels). Each lane then adds its 4 results to rows
-// q..q+3 of its input in the block's LDS copy of the gradient. A wave owns II
-// inputs (disjoint gradient rows) and walks every point of the slice in a
-// fixed order, so each LDS word has a single writer and the sums are
-// deterministic. A block owns 4*II inputs and all N outputs of one slice; the
-// next chunk of points is loaded while the current one is computed.
+// qa..qa+3 of its input in an LDS copy of the gradient. A wave owns II
+// inputs (disjoint gradient rows) and walks its points in a fixed order: each
+// LDS word has a single writer and the sums are deterministic. Points go in
+// pairs, so one point's matrix products overlap the other's
+// read-add-write. The 4 waves of a block are WI input groups times WP = 4/WI
+// point groups (WI < 4 when the layer has few inputs); each point group
+// takes every WP-th point of the slice into its own gradient copy, and the
+// copies are summed in order at the end. A block owns WI*II inputs and all
+// N outputs of one slice; the next chunk of points is loaded while the
+// current one is computed.
 // ---------------------------------------------------------------------------
 template <int NQ> constexpr int dw_pc() { return NQ >= 32 ? 8 : 16; }
 
-template <int O0, int O1, bool FIRST, int NQ>
+template <int O0, int O1, bool FIRST, int NQ, int II>
 __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
                                               const float *__restrict__ ybar,
                                               float *__restrict__ part, int64_t n, int win,
-                                              int nsplit, GridP<float> g)
+                                              int nsplit, int WI, GridP<float> g)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int CP = C <= 4 ? 4 : 8;       // padded channel stride in LDS
     constexpr int N = 4 * NQ;
-    constexpr int GS = N + 1;                // gradient row stride (spreads banks)
-    constexpr int II = 64 / NQ;              // inputs per wave (II * N = 256)
-    constexpr int IB = 4 * II;               // inputs per block
+    constexpr int GS = N;                    // gradient row stride
+    // input stride: 4*JC words of padding put the 8 blocks of a half-wave
+    // (8/JC inputs x JC output chunks x 4 columns) on 32 distinct banks
+    // whatever their rows
+    constexpr int IB = 4 * II;               // staged inputs (WI * II of them real)
     constexpr int JC = 16 / II;              // 4-output chunks per MFMA
     constexpr int PASSES = NQ / JC;
     constexpr int PC = dw_pc<NQ>();
-    constexpr int JS = IB * CP + 1;          // staged jets: stride per point
-    constexpr int YS = N * CP + 1;           // staged bars: stride per point
+    constexpr int JS = IB * CP + 4;          // staged jets: stride per point
+    constexpr int YS = N * CP + 4;           // staged bars: stride per point
     constexpr int EJ = C * IB * PC, EY = C * N * PC;
     constexpr int RJ = (EJ + NT - 1) / NT, RY = (EY + NT - 1) / NT;
-    extern __shared__ float smem[];
+    static_assert(PASSES >= 1 && JC * PASSES == NQ, "tile shape");
+    extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
-    float *sG = smem;                                  // [IB * nb][GS], then 256 scratch words
-    float *sJ = sG + IB * nb * GS + NT;                // [PC][JS]
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
+    const int IS = nb * GS + 4 * JC;
+    float *sG = smem;                                  // [WP][WI*II][IS]
+    float *sJ = sG + IB * IS;                          // [PC][JS]
     float *sY = sJ + PC * JS;                          // [PC][YS]
 
+    const int WP = 4 / WI, IBe = WI * II;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int blk = lane >> 2, s = lane & 3;
-    const int ii = wv * II + blk / JC, jc = blk % JC;  // block-local input of this lane
-    const int i0 = blockIdx.x * IB;
-    const bool iok = i0 + ii < win;
-    const int trash = IB * nb * GS + threadIdx.x;      // this lane's scratch word
-    const int lane_row = ii * nb * GS;                 // first gradient row of this lane's input
-    const int colbase = 4 * jc + s;
+    const int wi = wv % WI, wp = wv / WI;
+    const int ii = wi * II + blk / JC, jc = blk % JC;  // block-local input of this lane
+    const int i0 = blockIdx.x * IBe;
     const int split = blockIdx.y;
     const int64_t per = ((n + nsplit - 1) / nsplit + PC - 1) / PC * PC;
     const int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
-    for (int e = threadIdx.x; e < IB * nb * GS + NT; e += NT) sG[e] = 0.f;
+    for (int e = threadIdx.x; e < IB * IS; e += NT) sG[e] = 0.f;
+    float *gbase = sG + (wp * IBe + ii) * IS + 4 * jc + s;
 
     float rj[RJ], ry[RY];
     auto load = [&](int64_t pc) {
@@ -436,26 +467,74 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
             const int e = threadIdx.x + k * NT;
             const int pp = e % PC, rest = e / PC, il = rest % IB, c = rest / IB;
             const int64_t p = pc + pp;
-            float v = 0.f;
-            if (e < EJ && p < pe && i0 + il < win) {
-                if constexpr (FIRST) {
-                    float zj[C];
-                    input_jets<float, O0, O1>(zin, p, i0 + il, zj);
-                    v = zj[c];
-                } else {
-                    v = zin[((int64_t)c * win + i0 + il) * n + p];
-                }
+            const bool ok = e < EJ && p < pe && il < IBe && i0 + il < win;
+            const int ic = ok ? i0 + il : 0;
+            const int64_t pq = ok ? p : 0;
+            float v;
+            if constexpr (FIRST) {
+                float zj[C];
+                input_jets<float, O0, O1>(zin, pq, ic, zj);
+                v = zj[c];
+            } else {
+                v = zin[(int64_t)(c * win + ic) * n + pq];
             }
-            rj[k] = v;
+            rj[k] = ok ? v : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int e = threadIdx.x + k * NT;
             const int pp = e % PC, rest = e / PC, j = rest % N, c = rest / N;
             const int64_t p = pc + pp;
-            ry[k] = (e < EY && p < pe) ? ybar[((int64_t)c * N + j) * n + p] : 0.f;
+            const bool ok = e < EY && p < pe;
+            const float y = ybar[(int64_t)((ok ? c : 0) * N + (ok ? j : 0)) * n + (ok ? p : 0)];
+            ry[k] = ok ? y : 0.f;
         }
     };
+    // products of point pp for this lane's input: d[pass][t] (column s); the
+    // passes are interleaved so that consecutive MFMAs are independent
+    auto products = [&](int pp, f4 *d) -> int {
+        float zj[CP];
+#pragma unroll
+        for (int c4 = 0; c4 < CP / 4; ++c4) {
+            const f4 z4 = *reinterpret_cast<const f4 *>(sJ + pp * JS + ii * CP + 4 * c4);
+            zj[4 * c4 + 0] = z4[0]; zj[4 * c4 + 1] = z4[1]; zj[4 * c4 + 2] = z4[2]; zj[4 * c4 + 3] = z4[3];
+        }
+        const float zt = zj[0] * inv_w + zoff;
+        const int qa = window_k3(zt, nb);
+        float v[3], A[C];
+        bump_k3m4<2>(zt, qa + s, inv_w, v);      // this lane's row: window row t = s
+        features<float, O0, O1>(v, zj, A);
+        float yv[PASSES][CP];
+#pragma unroll
+        for (int q = 0; q < PASSES; ++q)
+#pragma unroll
+            for (int c4 = 0; c4 < CP / 4; ++c4) {
+                const f4 y4 = *reinterpret_cast<const f4 *>(sY + pp * YS + (4 * (q * JC + jc) + s) * CP + 4 * c4);
+                yv[q][4 * c4 + 0] = y4[0]; yv[q][4 * c4 + 1] = y4[1];
+                yv[q][4 * c4 + 2] = y4[2]; yv[q][4 * c4 + 3] = y4[3];
+            }
+#pragma unroll
+        for (int q = 0; q < PASSES; ++q) d[q] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int q = 0; q < PASSES; ++q) d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[c], yv[q][c], d[q], 0, 0, 0);
+        return qa;
+    };
+    // rows qa..qa+3 of this lane's input: all reads, then all writes
+    auto accumulate = [&](int qa, const f4 *d) {
+        float *gp = gbase + qa * GS;
+        float old[PASSES][4];
+#pragma unroll
+        for (int q = 0; q < PASSES; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) old[q][r] = gp[r * GS + 4 * q * JC];
+#pragma unroll
+        for (int q = 0; q < PASSES; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gp[r * GS + 4 * q * JC] = old[q][r] + d[q][r];
+    };
+
     if (ps < pe) load(ps);
     for (int64_t pc = ps; pc < pe; pc += PC) {
         __syncthreads();
@@ -474,72 +553,45 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         __syncthreads();
         if (pc + PC < pe) load(pc + PC);         // next chunk in flight during this one
         const int npts = (int)min<int64_t>(PC, pe - pc);
-        for (int pp = 0; pp < npts; ++pp) {
-            float zj[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) zj[c] = sJ[pp * JS + ii * CP + c];
-            const float zt = zeta_of(g, zj[0]);
-            const int q = interval_of(g, zt);
-            float v[3], A[C];
-            hr_bump<float, 2, 4>(g, zt, q + s, v);     // this lane's row: live function t = s
-            features<float, O0, O1>(v, zj, A);
-            f4 d[PASSES];
-#pragma unroll
-            for (int ps_ = 0; ps_ < PASSES; ++ps_) {
-                const int jb = 4 * (ps_ * JC + jc);
-                const float *yp = sY + pp * YS + (jb + s) * CP;
-                d[ps_] = (f4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    d[ps_] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[c], yp[c], d[ps_], 0, 0, 0);
-            }
-            // each (input, column) word belongs to one lane of one wave:
-            // plain read-add-write, no atomics. All reads are issued before
-            // any write; a row outside the basis goes to this lane's own
-            // scratch word, so the live addresses are all distinct.
-            int addr[PASSES][4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int b = q + r;
-                // all-ones when row b of this input is a live gradient row
-                const int keep = -(int)(iok & ((unsigned)b < (unsigned)nb));
-#pragma unroll
-                for (int ps_ = 0; ps_ < PASSES; ++ps_) {
-                    const int a = lane_row + b * GS + 4 * (ps_ * JC) + colbase;
-                    addr[ps_][r] = trash + ((a - trash) & keep);
-                }
-            }
-            float old[PASSES][4];
-#pragma unroll
-            for (int ps_ = 0; ps_ < PASSES; ++ps_)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) old[ps_][r] = sG[addr[ps_][r]];
-#pragma unroll
-            for (int ps_ = 0; ps_ < PASSES; ++ps_)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sG[addr[ps_][r]] = old[ps_][r] + d[ps_][r];
+        int pp = wp;
+        for (; pp + WP < npts; pp += 2 * WP) {
+            f4 d0[PASSES], d1[PASSES];
+            const int q0 = products(pp, d0);
+            const int q1 = products(pp + WP, d1);
+            accumulate(q0, d0);
+            accumulate(q1, d1);
+        }
+        if (pp < npts) {
+            f4 d0[PASSES];
+            const int q0 = products(pp, d0);
+            accumulate(q0, d0);
         }
     }
     __syncthreads();
     const int64_t KN = (int64_t)win * nb * N;
-    for (int e = threadIdx.x; e < IB * nb * N; e += NT) {
+    const int gcopy = IBe * IS;
+    for (int e = threadIdx.x; e < IBe * nb * N; e += NT) {
         const int row = e / N, col = e % N;
-        if (i0 + row / nb >= win) continue;
-        part[split * KN + (int64_t)(i0 * nb + row) * N + col] = sG[row * GS + col];
+        const int il = row / nb, b = row % nb;
+        if (i0 + il >= win) continue;
+        const int at = il * IS + b * GS + col;
+        float sum = sG[at];
+        for (int w = 1; w < WP; ++w) sum += sG[w * gcopy + at];
+        part[split * KN + (int64_t)(i0 * nb + row) * N + col] = sum;
     }
 }
 
-static size_t dw_bs_lds(int C, int nb, int N)
+static size_t dw_bs_lds(int C, int nb, int N, int II)
 {
-    const int CP = C <= 4 ? 4 : 8, IB = 4 * (256 / N), PC = N >= 128 ? 8 : 16;
-    return sizeof(float) * ((size_t)IB * nb * (N + 1) + NT + (size_t)PC * (IB * CP + 1) +
-                            (size_t)PC * (N * CP + 1));
+    const int CP = C <= 4 ? 4 : 8, IB = 4 * II, PC = N >= 128 ? 8 : 16, JC = 16 / II;
+    return sizeof(float) *
+           ((size_t)IB * (nb * N + 4 * JC) + (size_t)PC * (IB * CP + 4) + (size_t)PC * (N * CP + 4));
 }
 
 // ---------------------------------------------------------------------------
 // last layer (one output): plain vector-ALU kernels
 // ---------------------------------------------------------------------------
-// u_c[p] = sum_i sum_t W[i*nb + q + t] * A_c(p, i, t); one thread per point
+// u_c[p] = sum_i sum_t W[i*nb + qa + t] * A_c(p, i, t); one thread per point
 template <int O0, int O1>
 __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
                                                  const float *__restrict__ W,
@@ -549,6 +601,7 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
     constexpr int C = Ch<O0, O1>::C;
     extern __shared__ float sW[];
     const int nb = g.nb;
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     for (int e = threadIdx.x; e < win * nb; e += NT) sW[e] = W[e];
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -568,16 +621,14 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u;
             if (i >= win) break;
-            const float zt = zeta_of(g, zj[u][0]);
-            const int q = interval_of(g, zt);
+            const float zt = zj[u][0] * inv_w + zoff;
+            const int qa = window_k3(zt, nb);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int b = q + t;
-                if (b < 0 || b >= nb) continue;
                 float v[3], A[C];
-                hr_bump<float, 2, 4>(g, zt, b, v);
+                bump_k3m4<2>(zt, qa + t, inv_w, v);
                 features<float, O0, O1>(v, zj[u], A);
-                const float w = sW[i * nb + b];
+                const float w = sW[i * nb + qa + t];
 #pragma unroll
                 for (int c = 0; c < C; ++c) acc[c] += w * A[c];
             }
@@ -601,6 +652,7 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
     const int i = (int)(e / n);
     const int64_t p = e % n;
     const int nb = g.nb;
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     float zj[C], yb[C], zb[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -608,15 +660,13 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
         yb[c] = ybar[(int64_t)c * n + p];
         zb[c] = 0.f;
     }
-    const float zt = zeta_of(g, zj[0]);
-    const int q = interval_of(g, zt);
+    const float zt = zj[0] * inv_w + zoff;
+    const int qa = window_k3(zt, nb);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int b = q + t;
-        if (b < 0 || b >= nb) continue;
         float v[4], Ab[C];
-        hr_bump<float, 3, 4>(g, zt, b, v);
-        const float w = W[i * nb + b];
+        bump_k3m4<3>(zt, qa + t, inv_w, v);
+        const float w = W[i * nb + qa + t];
 #pragma unroll
         for (int c = 0; c < C; ++c) Ab[c] = w * yb[c];
         features_adjoint<float, O0, O1>(v, zj, Ab, zb);
@@ -638,6 +688,7 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
     constexpr int IB = NT / DL_SL;        // inputs per block
     __shared__ float sacc[NT][33];
     const int nb = g.nb;
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     const int li = threadIdx.x / DL_SL, sl = threadIdx.x % DL_SL;
     const int i = blockIdx.x * IB + li;
     const int split = blockIdx.y;
@@ -660,19 +711,17 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (p0 + (int64_t)u * DL_SL >= pe) break;
-                const float zt = zeta_of(g, zj[u][0]);
-                const int q = interval_of(g, zt);
+                const float zt = zj[u][0] * inv_w + zoff;
+                const int qa = window_k3(zt, nb);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int b = q + t;
-                    if (b < 0 || b >= nb) continue;
                     float v[3], A[C];
-                    hr_bump<float, 2, 4>(g, zt, b, v);
+                    bump_k3m4<2>(zt, qa + t, inv_w, v);
                     features<float, O0, O1>(v, zj[u], A);
                     float sum = 0.f;
 #pragma unroll
                     for (int c = 0; c < C; ++c) sum += A[c] * yb[u][c];
-                    sacc[threadIdx.x][b] += sum;
+                    sacc[threadIdx.x][qa + t] += sum;
                 }
             }
         }
@@ -710,25 +759,52 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
     default: return hipErrorInvalidValue;                         \
     }
 
+#define HRK_II_SWITCH(II_, ...)                                   \
+    switch (II_) {                                                \
+    case 2: { constexpr int II = 2; __VA_ARGS__; } break;         \
+    case 4: { constexpr int II = 4; __VA_ARGS__; } break;         \
+    case 8: { constexpr int II = 8; __VA_ARGS__; } break;         \
+    default: return hipErrorInvalidValue;                         \
+    }
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+// Inputs per wave of the weight-gradient kernel: the largest of 8, 4, 2 whose
+// block fits two blocks per CU (else one), with at least one output chunk
+// per pass. HRKAN_DW_II (2, 4 or 8) overrides it for tile tuning.
+static int dw_ii(LayerShape ls, int C)
+{
+    static int forced = -1;
+    if (forced < 0) {
+        const char *e = getenv("HRKAN_DW_II");
+        forced = (e && (atoi(e) == 2 || atoi(e) == 4 || atoi(e) == 8)) ? atoi(e) : 0;
+    }
+    const int NQ = ls.wout / 4;
+    if (forced && 16 / forced <= NQ && dw_bs_lds(C, ls.nb, ls.wout, forced) <= LDS_MAX) return forced;
+    for (size_t cap : {LDS_MAX / 2, LDS_MAX})
+        for (int ii : {8, 4, 2})
+            if (16 / ii <= NQ && dw_bs_lds(C, ls.nb, ls.wout, ii) <= cap) return ii;
+    return 0;
+}
+
 bool bs32_supported(LayerShape ls)
 {
-    if (ls.nb < 2 || ls.nb > 32) return false;
+    if (ls.nb < 4 || ls.nb > 32) return false;
     if (ls.wout == 1) return true;
     if (ls.wout != 32 && ls.wout != 64 && ls.wout != 128) return false;
-    return dw_bs_lds(5, ls.nb, ls.wout) <= 160 * 1024;
+    return dw_ii(ls, 5) > 0 && dw_ii(ls, 4) > 0 && dw_ii(ls, 1) > 0;
 }
 
 // Raise a kernel's dynamic-LDS limit once (outside any graph capture: the
 // first launch of each kernel happens eagerly).
-static void set_lds_limit(const void *kf, size_t bytes)
+static void set_lds_limit(const void *kf)
 {
     static const void *done[256];
     static int ndone = 0;
     for (int k = 0; k < ndone; ++k)
         if (done[k] == kf) return;
-    (void)hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
     if (ndone < 256) done[ndone++] = kf;
-    (void)bytes;
 }
 
 static int grid_blocks(int64_t tiles, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap)); }
@@ -738,8 +814,8 @@ static int grid_blocks(int64_t tiles, int cap) { return (int)std::max<int64_t>(1
 static void w_stage(LayerShape ls, int C, int &KI, size_t &bytes)
 {
     const size_t per_in = (size_t)ls.nb * (ls.wout + 4) * sizeof(float);
-    const size_t jets = (size_t)KJ * C * PB * sizeof(float);
-    size_t ki = (LDS_W_BYTES - jets) / per_in;
+    const size_t jets = (size_t)KJ * (C + 1) * TP * sizeof(float);
+    size_t ki = (LDS_FWD - jets) / per_in;
     if (ki >= (size_t)ls.win)
         ki = ls.win;
     else
@@ -762,17 +838,17 @@ hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float
     int KI;
     size_t sh;
     w_stage(ls, ch.C(), KI, sh);
-    const int grid = grid_blocks((n + PB - 1) / PB, cu_blocks);
+    const int grid = grid_blocks((n + TP - 1) / TP, cu_blocks);
     HRK_CH_SWITCH32(ch, {
         HRK_NQ_SWITCH(ls.wout, {
             if (first) {
                 auto kf = k_fwd_bs<O0, O1, true, NQ>;
-                set_lds_limit((const void *)kf, sh);
-                kf<<<grid, NT, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
+                set_lds_limit((const void *)kf);
+                kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
             } else {
                 auto kf = k_fwd_bs<O0, O1, false, NQ>;
-                set_lds_limit((const void *)kf, sh);
-                kf<<<grid, NT, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
+                set_lds_limit((const void *)kf);
+                kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
             }
         });
     });
@@ -793,27 +869,46 @@ hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const
     int KI;
     size_t sh;
     w_stage(ls, ch.C(), KI, sh);
-    const int grid = grid_blocks((n + PB - 1) / PB, cu_blocks);
+    const int grid = grid_blocks((n + TP - 1) / TP, cu_blocks);
     HRK_CH_SWITCH32(ch, {
         HRK_NQ_SWITCH(ls.wout, {
             auto kf = k_dx_bs<O0, O1, NQ>;
-            set_lds_limit((const void *)kf, sh);
-            kf<<<grid, NT, sh, st>>>(zin, ybar, W, zbar, n, ls.win, KI, g);
+            set_lds_limit((const void *)kf);
+            kf<<<grid, NT8, sh, st>>>(zin, ybar, W, zbar, n, ls.win, KI, g);
         });
     });
     return hipGetLastError();
 }
 
+// Weight-gradient tile: II inputs per wave, WI waves along inputs. Few
+// inputs (the first layer has 2) take a small II and WI < 4, and the spare
+// waves split the points instead.
+struct DwTile {
+    int II, WI;
+};
+static DwTile dw_tile(LayerShape ls, int C)
+{
+    int ii = dw_ii(ls, C);
+    if (ii == 0) return {0, 0};
+    while (ii > 2 && ii / 2 >= ls.win && 16 / (ii / 2) <= ls.wout / 4) ii /= 2;
+    const int groups = (ls.win + ii - 1) / ii;
+    const int wi = groups >= 4 ? 4 : groups >= 2 ? 2 : 1;
+    return {ii, wi};
+}
+
 int dw_bs32_splits(int64_t n, LayerShape ls)
 {
     if (n <= 0) return 0;
-    // enough blocks to fill the chip, but at least 256 points per slice
-    const int64_t maxs = std::max<int64_t>(1, n / 128);
+    // about two blocks per CU, with at least 32 points per slice
+    const int64_t maxs = std::max<int64_t>(1, n / 32);
     int64_t tiles;
-    if (ls.wout == 1)
+    if (ls.wout == 1) {
         tiles = (ls.win + NT / DL_SL - 1) / (NT / DL_SL);
-    else
-        tiles = (ls.win + 4 * (256 / ls.wout) - 1) / (4 * (256 / ls.wout));
+    } else {
+        const DwTile t = dw_tile(ls, 4);
+        const int ib = std::max(1, t.II * t.WI);
+        tiles = (ls.win + ib - 1) / ib;
+    }
     const int64_t s = (512 + tiles - 1) / tiles;
     return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(s, maxs), 1024));
 }
@@ -828,20 +923,27 @@ hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float 
         });
         return hipGetLastError();
     }
+    const DwTile tl = dw_tile(ls, ch.C());
+    if (tl.II == 0) return hipErrorInvalidValue;
+    const int ibe = tl.II * tl.WI;
+    const dim3 grid((unsigned)((ls.win + ibe - 1) / ibe), (unsigned)nsplit);
+    const int wi = tl.WI;
     HRK_CH_SWITCH32(ch, {
         HRK_NQ_SWITCH(ls.wout, {
-            constexpr int IB = 4 * (64 / NQ);
-            dim3 grid((unsigned)((ls.win + IB - 1) / IB), (unsigned)nsplit);
-            const size_t sh = dw_bs_lds(ch.C(), ls.nb, ls.wout);
-            if (first) {
-                auto kf = k_dw_bs<O0, O1, true, NQ>;
-                set_lds_limit((const void *)kf, sh);
-                kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, g);
-            } else {
-                auto kf = k_dw_bs<O0, O1, false, NQ>;
-                set_lds_limit((const void *)kf, sh);
-                kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, g);
-            }
+            HRK_II_SWITCH(tl.II, {
+                if constexpr (16 / II <= NQ) {
+                    const size_t sh = dw_bs_lds(ch.C(), ls.nb, ls.wout, II);
+                    if (first) {
+                        auto kf = k_dw_bs<O0, O1, true, NQ, II>;
+                        set_lds_limit((const void *)kf);
+                        kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g);
+                    } else {
+                        auto kf = k_dw_bs<O0, O1, false, NQ, II>;
+                        set_lds_limit((const void *)kf);
+                        kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g);
+                    }
+                }
+            });
         });
     });
     return hipGetLastError();

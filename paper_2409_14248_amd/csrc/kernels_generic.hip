@@ -396,8 +396,18 @@ __global__ __launch_bounds__(NT) void k_reduce_splits(const T *__restrict__ part
     const int el = threadIdx.x % RD_EB, sl = threadIdx.x / RD_EB;
     const int64_t e = (int64_t)blockIdx.x * RD_EB + el;
     double s = 0.0;
-    if (e < count)
-        for (int k = sl; k < nsplit; k += RD_SL) s += (double)part[(int64_t)k * count + e];
+    if (e < count) {
+        // slices sl, sl + RD_SL, ... in increasing order; 8 loads in flight
+        int k = sl;
+        for (; k + 7 * RD_SL < nsplit; k += 8 * RD_SL) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(k + u * RD_SL) * count + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        for (; k < nsplit; k += RD_SL) s += (double)part[(int64_t)k * count + e];
+    }
     sh[sl][el] = s;
     __syncthreads();
     if (sl == 0 && e < count) {

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -150,13 +151,73 @@ int cu_blocks()
     return cached;
 }
 
-static int64_t max_part_elems(const NetInfo &ni, int64_t n_a, int64_t n_b)
+// A second stream per (device, caller stream): the boundary point set runs
+// on it concurrently with the interior set, joined by events. Streams and
+// events are created on first use and kept for the life of the process;
+// the stream has the default priority.
+int get_fork(hipStream_t st, Fork **out)
+{
+    struct Entry {
+        int dev;
+        hipStream_t st;
+        Fork f;
+    };
+    static std::mutex mu;
+    static Entry tab[64];
+    static int ntab = 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(mu);
+    for (int k = 0; k < ntab; ++k)
+        if (tab[k].dev == dev && tab[k].st == st) {
+            *out = &tab[k].f;
+            return HRKAN_OK;
+        }
+    if (ntab == 64) {
+        *out = nullptr;   // table full: the caller runs both sets on st
+        return HRKAN_OK;
+    }
+    Entry &en = tab[ntab];
+    en.dev = dev;
+    en.st = st;
+    if ((e = hipStreamCreateWithFlags(&en.f.side, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "side stream");
+    if ((e = hipEventCreateWithFlags(&en.f.fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&en.f.join, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "fork events");
+    ++ntab;
+    *out = &en.f;
+    return HRKAN_OK;
+}
+
+int fork_to(Fork *f, hipStream_t st)
+{
+    hipError_t e = hipEventRecord(f->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(f->side, f->fork, 0);
+    return e == hipSuccess ? HRKAN_OK : hip_fail(e, "stream fork");
+}
+
+int join_from(Fork *f, hipStream_t st)
+{
+    hipError_t e = hipEventRecord(f->join, f->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, f->join, 0);
+    return e == hipSuccess ? HRKAN_OK : hip_fail(e, "stream join");
+}
+
+// Weight-gradient partial slices of layer l for point sets of n_a and n_b
+// points (elements). Every layer has a region of its own, so that the two
+// sets' reverse passes can run concurrently and reduce at the end.
+int64_t part_layer_elems(const NetInfo &ni, int l, int64_t n_a, int64_t n_b)
+{
+    const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+    return (int64_t)(dw_splits(ni, l, n_a) + dw_splits(ni, l, n_b)) * kn;
+}
+
+static int64_t part_elems_total(const NetInfo &ni, int64_t n_a, int64_t n_b)
 {
     int64_t m = 0;
-    for (int l = 0; l < ni.L; ++l) {
-        const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
-        m = std::max(m, (int64_t)(dw_splits(ni, l, n_a) + dw_splits(ni, l, n_b)) * kn);
-    }
+    for (int l = 0; l < ni.L; ++l) m += part_layer_elems(ni, l, n_a, n_b);
     return m;
 }
 
@@ -182,7 +243,7 @@ WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
     L.bars1 = take(E * 5 * (size_t)ni.maxw * nmax);
     L.bbars0 = take(E * (size_t)ni.maxw * n_bc);
     L.bbars1 = take(E * (size_t)ni.maxw * n_bc);
-    L.part_elems = max_part_elems(ni, std::max(n_int, n_bc), std::min(n_int, n_bc));
+    L.part_elems = part_elems_total(ni, n_int, n_bc);
     L.part = take(E * (size_t)L.part_elems);
     L.total = o;
     return L;
@@ -257,69 +318,95 @@ struct RevSet {
     T *bar0, *bar1;
 };
 
+// Reverse pass of one point set: per layer (last to first) the weight-gradient
+// slices into that layer's partial region at offset off[l], then the input
+// bars of the layer below.
+#define TRY(x)                          \
+    do {                                \
+        int rc_ = (x);                  \
+        if (rc_ != HRKAN_OK) return rc_; \
+    } while (0)
+
 template <typename T>
-int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, int nsets,
-                 T *const *gW, int accumulate, T *part, hipStream_t st)
+int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const int64_t *off, T *part,
+                hipStream_t st)
 {
     const GridP<T> g = make_grid<T>(ni);
-    const T *ybar[2] = {nullptr, nullptr};
-    for (int s = 0; s < nsets; ++s) ybar[s] = sets[s].seed;
+    const T *ybar = S.seed;
     for (int l = ni.L - 1; l >= 0; --l) {
         const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
-        const int64_t kn = (int64_t)ls.win * ls.nb * ls.wout;
-        int tot = 0;
-        for (int s = 0; s < nsets; ++s) {
-            const RevSet<T> &S = sets[s];
-            if (S.n <= 0) continue;
-            const int ns = dw_splits(ni, l, S.n);
-            const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
-            hipError_t e;
-            {
-                ProfScope ps("dw", l, st);
-                T *dst = part + (int64_t)tot * kn;
-                if constexpr (std::is_same<T, float>::value) {
-                    if (use_bs32(ni, l))
-                        e = launch_dw_bs32(S.ch, l == 0, zin, ybar[s], dst, ns, S.n, ls, g, st);
-                    else
-                        e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar[s], dst, ns, S.n, ls, g, st);
-                } else {
-                    e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar[s], dst, ns, S.n, ls, g, st);
-                }
+        const int ns = dw_splits(ni, l, S.n);
+        const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
+        hipError_t e;
+        {
+            ProfScope ps("dw", l, st);
+            T *dst = part + off[l];
+            if constexpr (std::is_same<T, float>::value) {
+                if (use_bs32(ni, l))
+                    e = launch_dw_bs32(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, st);
+                else
+                    e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, st);
+            } else {
+                e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, st);
             }
-            if (e != hipSuccess) return hip_fail(e, "weight-gradient launch");
-            tot += ns;
         }
-        if (tot == 0) {
-            if (!accumulate) {
-                hipError_t e = launch_reduce_splits<T>(part, 0, kn, gW[l], 0, st);
-                if (e != hipSuccess) return hip_fail(e, "gW clear");
+        if (e != hipSuccess) return hip_fail(e, "weight-gradient launch");
+        if (l == 0) break;
+        T *zbar = (ybar == S.bar0) ? S.bar1 : S.bar0;
+        {
+            ProfScope ps("dx", l, st);
+            if constexpr (std::is_same<T, float>::value) {
+                if (use_bs32(ni, l))
+                    e = launch_dx_bs32(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, cu_blocks(), st);
+                else
+                    e = launch_dx_generic<T>(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, st);
+            } else {
+                e = launch_dx_generic<T>(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, st);
             }
+        }
+        if (e != hipSuccess) return hip_fail(e, "input-bar launch");
+        ybar = zbar;
+    }
+    return HRKAN_OK;
+}
+
+// Reverse pass of up to two point sets sharing W. Layer l's partial region
+// holds all slices of set 0, then all of set 1; with a fork the second set
+// runs on the side stream. The regions are reduced into gW at the end, each
+// element summed over its slices in that fixed order.
+template <typename T>
+int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, int nsets,
+                 T *const *gW, int accumulate, T *part, hipStream_t st, Fork *fk)
+{
+    const int64_t n0 = nsets > 0 ? sets[0].n : 0, n1 = nsets > 1 ? sets[1].n : 0;
+    int64_t base[HRKAN_MAX_LAYERS], off0[HRKAN_MAX_LAYERS], off1[HRKAN_MAX_LAYERS];
+    int tot[HRKAN_MAX_LAYERS];
+    int64_t o = 0;
+    for (int l = 0; l < ni.L; ++l) {
+        const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+        const int s0 = dw_splits(ni, l, n0), s1 = dw_splits(ni, l, n1);
+        base[l] = o;
+        off0[l] = o;
+        off1[l] = o + (int64_t)s0 * kn;
+        tot[l] = s0 + s1;
+        o += part_layer_elems(ni, l, n0, n1);
+    }
+    const bool split = fk && n0 > 0 && n1 > 0;
+    if (split) TRY(fork_to(fk, st));
+    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st));
+    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st));
+    if (split) TRY(join_from(fk, st));
+    for (int l = ni.L - 1; l >= 0; --l) {
+        const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+        hipError_t e;
+        if (tot[l] == 0) {
+            if (accumulate) continue;
+            e = launch_reduce_splits<T>(part, 0, kn, gW[l], 0, st);   // writes zeros
         } else {
             ProfScope ps("reduce", l, st);
-            hipError_t e = launch_reduce_splits<T>(part, tot, kn, gW[l], accumulate, st);
-            if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+            e = launch_reduce_splits<T>(part + base[l], tot[l], kn, gW[l], accumulate, st);
         }
-        if (l == 0) break;
-        for (int s = 0; s < nsets; ++s) {
-            const RevSet<T> &S = sets[s];
-            if (S.n <= 0) continue;
-            T *zbar = (ybar[s] == S.bar0) ? S.bar1 : S.bar0;
-            const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
-            hipError_t e;
-            {
-                ProfScope ps("dx", l, st);
-                if constexpr (std::is_same<T, float>::value) {
-                    if (use_bs32(ni, l))
-                        e = launch_dx_bs32(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, cu_blocks(), st);
-                    else
-                        e = launch_dx_generic<T>(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, st);
-                } else {
-                    e = launch_dx_generic<T>(S.ch, zin, ybar[s], W[l], zbar, S.n, ls, g, st);
-                }
-            }
-            if (e != hipSuccess) return hip_fail(e, "input-bar launch");
-            ybar[s] = zbar;
-        }
+        if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
     }
     return HRKAN_OK;
 }
@@ -354,12 +441,6 @@ int check_pde(const hrkan_pde_desc *pde)
 }
 
 uint32_t pde_mask(int kind) { return kind == HRKAN_POISSON2D ? HRKAN_MASK_POISSON : HRKAN_MASK_BURGERS; }
-
-#define TRY(x)                          \
-    do {                                \
-        int rc_ = (x);                  \
-        if (rc_ != HRKAN_OK) return rc_; \
-    } while (0)
 
 }  // namespace
 
@@ -529,7 +610,7 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
         RevSet<double> s{ch, (const double *)x, n, (const double *)seed, (const double *)saved,
                          (double *)(w + L.bars0), (double *)(w + L.bars1)};
         return reverse_impl<double>(ni, (const double *const *)W, &s, 1, (double *const *)gW_out,
-                                    accumulate, (double *)(w + L.part), stream);
+                                    accumulate, (double *)(w + L.part), stream, nullptr);
     }
     if (ni.dtype == HRKAN_BF16)
         return bf16_backward(ni, ch, W, (const float *)x, n, (const float *)seed,
@@ -538,7 +619,7 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
     RevSet<float> s{ch, (const float *)x, n, (const float *)seed, (const float *)saved,
                     (float *)(w + L.bars0), (float *)(w + L.bars1)};
     return reverse_impl<float>(ni, (const float *const *)W, &s, 1, (float *const *)gW_out, accumulate,
-                               (float *)(w + L.part), stream);
+                               (float *)(w + L.part), stream, nullptr);
 }
 
 int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
@@ -574,12 +655,17 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         T *sv_int = (T *)(w + L.sv_int), *jets = (T *)(w + L.jets_int);
         T *sv_bc = (T *)(w + L.sv_bc), *ubc = (T *)(w + L.ubc);
         T *seed_int = (T *)(w + L.seed_int), *seed_bc = (T *)(w + L.seed_bc);
+        // boundary set on the side stream, interior set on the caller's
+        Fork *fk = nullptr;
+        if (ni_ > 0 && nb_ > 0) TRY(get_fork(stream, &fk));
+        if (fk) TRY(fork_to(fk, stream));
+        if (nb_ > 0)
+            TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
+                                nullptr, nullptr, fk ? fk->side : stream));
         if (ni_ > 0)
             TRY(forward_impl<T>(ni, chi, (const T *const *)W, (const T *)pts->x_int, ni_, jets, sv_int,
                                 nullptr, nullptr, stream));
-        if (nb_ > 0)
-            TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
-                                nullptr, nullptr, stream));
+        if (fk) TRY(join_from(fk, stream));
         double *partials = (double *)(w + L.loss_part);
         hipError_t e;
         {
@@ -600,7 +686,7 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
             {chb, (const T *)pts->x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
         };
         return reverse_impl<T>(ni, (const T *const *)W, sets, 2, (T *const *)gW_out, 0,
-                               (T *)(w + L.part), stream);
+                               (T *)(w + L.part), stream, fk);
     };
     if (ni.dtype == HRKAN_F64) return run(double{});
     return run(float{});

@@ -38,6 +38,16 @@ int mask_cfg(uint32_t mask, ChanCfg *ch);
 template <typename T> GridP<T> make_grid(const NetInfo &ni);
 int64_t saved_elems(const NetInfo &ni, int C, int64_t n);
 int dw_splits(const NetInfo &ni, int l, int64_t n);
+int64_t part_layer_elems(const NetInfo &ni, int l, int64_t n_a, int64_t n_b);
+
+// Side stream and events of one caller stream (see get_fork).
+struct Fork {
+    hipStream_t side;
+    hipEvent_t fork, join;
+};
+int get_fork(hipStream_t st, Fork **out);
+int fork_to(Fork *f, hipStream_t st);      // side waits for st's work so far
+int join_from(Fork *f, hipStream_t st);    // st waits for side's work so far
 bool use_bs32(const NetInfo &ni, int l);
 int cu_blocks();
 WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc);
