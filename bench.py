@@ -5,16 +5,19 @@ A step is the whole hot path over one batch of synthetic collocation points:
 forward jets at the interior and boundary points, residual and loss, and the
 reverse pass to every weight (hrkan_step). Default workload: viscous Burgers
 (nu = 0.01/pi) with a [2,32,32,1] HRKAN, G = 10, k = 3, m = 4, 65,536 interior
-+ 4,096 initial/boundary points, FP32.
++ 4,096 initial/boundary points, FP32, inputs resident in HBM, the step
+replayed from a HIP graph.
 
 Prints ONE JSON line: interior collocation points per second over the timed
-steps (inputs resident in HBM), the roofline position of the dominant kernel
-(timed per launch with HIP events on the step's stream), and the CPU oracle
-timed on the host cores on a bounded sample of the same workload.
+steps, the roofline position of the dominant kernel (its launches timed with
+HIP events on the stream they run on), and the CPU oracle timed on the host
+cores on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,13 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PINN train-step collocation points/s (fwd jets+residual+bwd), bf16 vs fp32"
 
-# MI355X published peaks
-PEAK = {
-    "hbm_GBs": 8000.0,
-    "mfma_f32": 157.3, "mfma_f64": 78.6, "mfma_bf16": 2500.0,
-    # vector ALU without packed FP32: 256 CU x 64 lanes x 2 flop x 2.4 GHz
-    "alu_f32": 78.6, "alu_f64": 78.6,
-}
+# MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2409_14248_amd", "csrc", "kernels_bs32.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_burgers_c2_f32.md")
 
 
 def parse():
@@ -44,16 +45,20 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying a HIP graph")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def layer_flops(net, C, n, dense=True):
-    """Algorithmic flops of the three contractions of each layer for n points
-    with C jet channels: 2*C*K*N per point and contraction, K = w_in * n_b
-    (dense basis tensor, as the method states it)."""
+def layer_flops(net, C, n, live=False):
+    """Algorithmic flops of each contraction of each layer for n points with C
+    jet channels: 2*C*K*N per point, K = w_in * n_b (the dense basis-by-W
+    product the method defines). live=True counts only the k+1 non-zero
+    basis functions per input (K = w_in * (k+1)): the products the kernels
+    execute."""
     out = {}
     for l in range(net.n_layers):
-        K = net.widths[l] * (net.n_basis if dense else (net.k + 1))
+        K = net.widths[l] * ((net.k + 1) if live else net.n_basis)
         N = net.widths[l + 1]
         f = 2.0 * C * K * N * n
         out[f"fwd_l{l}"] = f
@@ -63,11 +68,34 @@ def layer_flops(net, C, n, dense=True):
     return out
 
 
+def kernel_flops(pr, C, live=False):
+    """Flops of every profiled launch name (interior names, and _bc names for
+    the boundary set with one channel)."""
+    out = dict(layer_flops(pr.net, C, pr.n_int, live))
+    for k, v in layer_flops(pr.net, 1, pr.n_bc, live).items():
+        out[k + "_bc"] = v
+    return out
+
+
+def traffic_record(kernel_name, launches_per_step):
+    """HBM bytes per launch of a kernel from the committed counter summary,
+    if that summary was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE) or not os.path.exists(KERNEL_SRC):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel source sha256:\s*([0-9a-f]{64})", txt)
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if not m or m.group(1) != cur:
+        return None
+    m = re.search(r"^\|\s*%s\s*\|\s*([0-9.eE+]+)\s*\|" % re.escape(kernel_name), txt, re.M)
+    return float(m.group(1)) if m else None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the data-parallel design over several GPUs is described, not built).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(how the step shards over several GPUs is described, not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -104,7 +132,7 @@ def main():
         ms = timed(step.replay, args.steps)
     loss = step.loss.cpu().numpy()
 
-    # per-kernel times over a second timed pass (events around every launch)
+    # per-kernel times: HIP events around every launch, on its own stream
     H.profile_enable(True)
     for _ in range(args.steps):
         step()
@@ -112,26 +140,32 @@ def main():
     prof = H.profile_read()
     H.profile_enable(False)
 
+    if args.calib_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
     C = H.mask_channels(H.pde_mask(pr.pde.kind))
-    dense = {k: v + layer_flops(pr.net, 1, pr.n_bc).get(k, 0.0)
-             for k, v in layer_flops(pr.net, C, pr.n_int).items()}
+    dense = kernel_flops(pr, C)
+    live = kernel_flops(pr, C, live=True)
     total_ms = sum(v[1] for v in prof.values()) / args.steps
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    dname, (dcnt, dms) = dom
+    contraction = {k: v for k, v in prof.items() if k in dense}
+    dname, (dcnt, dms) = max(contraction.items(), key=lambda kv: kv[1][1])
     per_launch_ms = dms / dcnt
     launches_per_step = dcnt / args.steps
-    flops_per_launch = dense.get(dname, 0.0) / launches_per_step
-    kind = {"f64": "f64", "f32": "f32", "bf16": "bf16"}[dtype]
-    if dtype == "bf16":
-        bound, peak = "mfma", PEAK["mfma_bf16"]
-    else:
-        bound, peak = "mfma", PEAK[f"mfma_{kind}"]
-    achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+    f_dense = dense[dname] / launches_per_step
+    f_live = live[dname] / launches_per_step
+    peak = PEAK[dtype]
+    achieved = f_dense / (per_launch_ms * 1e-3) / 1e12
+    achieved_live = f_live / (per_launch_ms * 1e-3) / 1e12
     roofline = {
-        "bound": bound, "kernel": dname, "achieved": round(achieved, 3), "peak": peak,
-        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-        "launch_ms": round(per_launch_ms, 5), "flops_per_launch": flops_per_launch,
-        "kernel_share": round(dms / args.steps / total_ms, 3),
+        "bound": "mfma", "kernel": dname, "achieved": round(achieved, 3), "peak": peak,
+        "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+        "traffic": traffic_record(dname, launches_per_step),
+        "flops_per_launch": f_dense, "launch_ms": round(per_launch_ms, 5),
+        "achieved_live": round(achieved_live, 3), "frac_live": round(achieved_live / peak, 4),
+        "live_flops_per_launch": f_live, "kernel_share": round(dms / args.steps / total_ms, 3),
     }
     step_flops = sum(dense.values())
 
@@ -146,12 +180,12 @@ def main():
             O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
             reps += 1
             el = time.time() - t
-            if el >= args.cpu_seconds or reps >= 3:
+            if el >= args.cpu_seconds or reps >= 30:
                 break
         cpu = {"value": round(reps * pr.n_int / el, 1), "unit": "points/s", "cores": O.num_threads(),
                "kind": "oracle",
-               "sample": f"{reps} full step(s) of {args.workload} ({pr.n_int}+{pr.n_bc} points), "
-                         f"FP64, {el:.1f} s"}
+               "sample": f"{reps} full FP64 step(s) of {args.workload} ({pr.n_int} interior + "
+                         f"{pr.n_bc} boundary points) in {el:.1f} s"}
 
     out = {
         "metric": METRIC,

@@ -71,6 +71,14 @@ static double round_feature(double a)
 
 static double round_store(double v) { return g_mode == 0 ? v : to_f32(v); }
 
+/* BF16 mode only: an output bar entering the input-bar contraction (with
+ * W) is the split operand, like a feature; entering the weight-gradient
+ * product (with a feature) it is the second operand, of which only the
+ * high BF16 piece is used for split <= 2. Other modes leave bars as
+ * stored. */
+static double round_bar_split(double v) { return g_mode == 2 ? round_feature(v) : v; }
+static double round_bar_hi(double v) { return g_mode == 2 ? to_bf16(to_f32(v)) : v; }
+
 /* one step of a contraction's running sum, acc + w * a; in the rounding
  * model it is rounded to FP32 as an FP32 fused multiply-add would (the
  * product of two FP32 values is exact in double: one rounding of the sum) */
@@ -209,8 +217,8 @@ static void bwd_point(int m, int nb, const double *s, const double *e,
                 double g = 0.0;
                 for (int q = 0; q < HRO_SLOTS; ++q) {
                     const double yb = ybar[q * wout + j];
-                    Ab[q] = acc_step(Ab[q], wrow[j], yb);   /* dL/dA = W * dL/dY */
-                    g += A[q] * yb;              /* dL/dW = A * dL/dY   */
+                    Ab[q] = acc_step(Ab[q], wrow[j], round_bar_split(yb));   /* dL/dA = W * dL/dY */
+                    g += A[q] * round_bar_hi(yb);                            /* dL/dW = A * dL/dY */
                 }
                 grow[j] += g;
             }

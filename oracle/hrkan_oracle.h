@@ -122,7 +122,10 @@ int hro_step(const hro_net *net, const hro_pde *pde, const double *const *W,
  *           in the reverse pass) is rounded to FP32;
  *   mode 2: as mode 1, and every basis feature is further replaced by the sum
  *           of its first `split` BF16 pieces (hi, then lo = the BF16 rounding
- *           of the remainder), each rounded to nearest even.
+ *           of the remainder), each rounded to nearest even; in the reverse
+ *           pass an output bar is split the same way where it multiplies W
+ *           (input bars) and rounded to its high BF16 piece where it
+ *           multiplies a feature (weight gradient).
  * Weights are never rounded here: callers pass already rounded weights. */
 void hro_set_rounding(int mode, int split);
 

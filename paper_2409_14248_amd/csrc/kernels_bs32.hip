@@ -38,7 +38,7 @@ constexpr int LDS_FWD = 78 * 1024;      // per 8-wave block: two blocks per CU
 
 // Waves per SIMD the 8-wave kernels are compiled for: two blocks per CU
 // (registers <= 128) when a point's channels fit one 4-row group.
-template <int O0, int O1> constexpr int fwd_waves() { return Ch<O0, O1>::C <= 4 ? 4 : 2; }
+template <int O0, int O1, int NQ> constexpr int fwd_waves() { return Ch<O0, O1>::C <= 4 ? 4 : 2; }
 
 // Broadcast lane T of each quad (DPP quad_perm [T,T,T,T]).
 template <int T>
@@ -111,14 +111,101 @@ __device__ __forceinline__ void stage_rows(float *sW, const float *__restrict__ 
     }
 }
 
-// A chunk of KJ inputs' jets for a tile of TP points, prefetched into
+// ---------------------------------------------------------------------------
+// BF16 products (S > 0). A product a*b of FP32 values is taken as S BF16
+// matrix-core products with FP32 accumulation: a = a_hi + a_lo and
+// b = b_hi + b_lo (round to nearest even), S = 1: a_hi b_hi; S = 2: adds
+// a_lo b_hi; S = 3: adds a_hi b_lo. In the forward and input-bar
+// contractions b is the weight; in the weight gradient a is the feature and
+// b the output bar. The 4x4x4 BF16 MFMA takes K = 4 per block: the 4 window
+// rows (forward), 4 outputs (input bars) or 4 jet channels (gradient).
+// ---------------------------------------------------------------------------
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// {a, b} rounded to BF16, a in the low half.
+__device__ __forceinline__ unsigned int pk_bf16(float a, float b)
+{
+    return __builtin_bit_cast(unsigned int, __builtin_convertvector((f2){a, b}, bf2));
+}
+__device__ __forceinline__ float bf16_lo_f(unsigned int w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi_f(unsigned int w) { return __uint_as_float(w & 0xffff0000u); }
+
+// hi and lo BF16 pieces of 4 FP32 values, packed as MFMA operands
+__device__ __forceinline__ void split4(const float *v, s4 &hi, s4 &lo)
+{
+    const unsigned int h0 = pk_bf16(v[0], v[1]), h1 = pk_bf16(v[2], v[3]);
+    const unsigned int l0 = pk_bf16(v[0] - bf16_lo_f(h0), v[1] - bf16_hi_f(h0));
+    const unsigned int l1 = pk_bf16(v[2] - bf16_lo_f(h1), v[3] - bf16_hi_f(h1));
+    hi = __builtin_bit_cast(s4, (u2){h0, h1});
+    lo = __builtin_bit_cast(s4, (u2){l0, l1});
+}
+__device__ __forceinline__ s4 hi4(const float *v)
+{
+    return __builtin_bit_cast(s4, (u2){pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])});
+}
+__device__ __forceinline__ s4 mk4(unsigned int a, unsigned int b) { return __builtin_bit_cast(s4, (u2){a, b}); }
+
+__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Stage weight rows of `nin` inputs starting at input i0 as BF16 row pairs:
+// word (il, b, j) = {W[(i0+il)*nb + b][j], W[(i0+il)*nb + b + 1][j]} for
+// b = 0..nb-2, row stride NS words. LO = true stores the low pieces
+// W - bf16(W) instead.
+template <int BLK, bool LO>
+__device__ __forceinline__ void stage_pairs(unsigned int *sP, const float *__restrict__ W, int i0, int nin,
+                                            int nb, int N, int NS)
+{
+    const int n4 = N / 4, np = nb - 1;
+    for (int e = threadIdx.x; e < nin * np * n4; e += BLK) {
+        const int c4 = e % n4, r = e / n4;
+        const int il = r / np, b = r % np;
+        const float *w0 = W + (size_t)((i0 + il) * nb + b) * N + 4 * c4;
+        const f4 a = *reinterpret_cast<const f4 *>(w0);
+        const f4 c = *reinterpret_cast<const f4 *>(w0 + N);
+        u4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned int h = pk_bf16(a[q], c[q]);
+            o[q] = LO ? pk_bf16(a[q] - bf16_lo_f(h), c[q] - bf16_hi_f(h)) : h;
+        }
+        *reinterpret_cast<u4 *>(sP + (il * np + b) * NS + 4 * c4) = o;
+    }
+}
+
+// Stage weight rows [r0, r0 + nrows) as BF16, row-major, NSH halfwords per
+// row (LO: the low pieces).
+template <int BLK, bool LO>
+__device__ __forceinline__ void stage_rows_bf16(unsigned short *sH, const float *__restrict__ W, int r0,
+                                                int nrows, int N, int NSH)
+{
+    const int n4 = N / 4;
+    for (int e = threadIdx.x; e < nrows * n4; e += BLK) {
+        const int r = e / n4, c4 = e % n4;
+        const f4 a = *reinterpret_cast<const f4 *>(W + (size_t)(r0 + r) * N + 4 * c4);
+        unsigned int h0 = pk_bf16(a[0], a[1]), h1 = pk_bf16(a[2], a[3]);
+        if (LO) {
+            h0 = pk_bf16(a[0] - bf16_lo_f(h0), a[1] - bf16_hi_f(h0));
+            h1 = pk_bf16(a[2] - bf16_lo_f(h1), a[3] - bf16_hi_f(h1));
+        }
+        *reinterpret_cast<u2 *>(sH + r * NSH + 4 * c4) = (u2){h0, h1};
+    }
+}
+
+// A chunk of KJ inputs' jets for a tile of TPC points, prefetched into
 // registers one chunk ahead and stored to LDS as [input][channel][point] with
 // C + 1 channel rows per input (the last one stays zero).
-template <int O0, int O1, bool FIRST, int BLK>
+template <int O0, int O1, bool FIRST, int BLK, int TPC>
 struct JetChunk {
     static constexpr int C = Ch<O0, O1>::C;
-    static constexpr int CS = (C + 1) * TP;     // floats per staged input
-    static constexpr int E = KJ * C * TP;
+    static constexpr int CS = (C + 1) * TPC;     // floats per staged input
+    static constexpr int E = KJ * C * TPC;
     static constexpr int R = (E + BLK - 1) / BLK;
     float r[R];
 
@@ -128,9 +215,9 @@ struct JetChunk {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int e = threadIdx.x + k * BLK;
-            const int pp = e % TP, rest = e / TP, c = rest % C, il = rest / C;
+            const int pp = e % TPC, rest = e / TPC, c = rest % C, il = rest / C;
             const int i = jc * KJ + il;
-            const int64_t p = tile * TP + pp;
+            const int64_t p = tile * TPC + pp;
             const bool ok = e < E && i < win && p < n;
             const int ic = ok ? i : 0;
             const int64_t pc = ok ? p : 0;
@@ -150,23 +237,29 @@ struct JetChunk {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int e = threadIdx.x + k * BLK;
-            if (e < E) sZ[e + (e / (C * TP)) * TP] = r[k];
+            if (e < E) sZ[e + (e / (C * TPC)) * TPC] = r[k];
         }
     }
     __device__ __forceinline__ static void zero_rows(float *sZ)
     {
-        for (int e = threadIdx.x; e < KJ * TP; e += BLK) sZ[(e / TP) * CS + C * TP + e % TP] = 0.f;
+        for (int e = threadIdx.x; e < KJ * TPC; e += BLK) sZ[(e / TPC) * CS + C * TPC + e % TPC] = 0.f;
     }
 };
 
 // ---------------------------------------------------------------------------
 // forward: zout[c][j][p] = sum_i sum_t W[i*nb + qa + t][j] * A_c(p, i, t)
-// Persistent 8-wave blocks walk tiles of 128 points (16 per wave); the
-// block's weight rows are staged once when they fit (KI >= win), else per
-// chunk of KI inputs. NQ = N/4; block column s owns outputs j = s*NQ + k.
+// Persistent 8-wave blocks walk tiles of points, 16 per wave; for N > 32
+// the waves also split the outputs into OG = N/32 groups (tiles of 128/OG
+// points), so a lane always holds 8 output quads. The block's weight rows
+// are staged once when they fit (KI >= win), else per chunk of KI inputs.
+// Block column s owns outputs j = og*32 + s*8 + k.
+// S = 0: FP32, one 4x4x1 MFMA per window row t (K = 1). S > 0: BF16, one
+// 4x4x4 MFMA per product term with K = the 4 window rows; the weights are
+// staged as BF16 row pairs, so a lane's B operand for output j is the two
+// words (qa, qa+1) and (qa+2, qa+3) of column j.
 // ---------------------------------------------------------------------------
-template <int O0, int O1, bool FIRST, int NQ>
-__global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_fwd_bs(const float *__restrict__ zin,
+template <int O0, int O1, bool FIRST, int NQ, int S>
+__global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const float *__restrict__ zin,
                                                    const float *__restrict__ W,
                                                    float *__restrict__ zout, int64_t n, int win,
                                                    int KI, GridP<float> g)
@@ -175,21 +268,37 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_fwd_bs(const flo
     constexpr int RG = (C + 3) / 4;
     constexpr int N = 4 * NQ;
     constexpr int NS = N + 4;
-    using JCk = JetChunk<O0, O1, FIRST, NT8>;
+    constexpr int OG = NQ / 8;               // output groups: the waves split the outputs
+    constexpr int NQW = NQ / OG;             // output quads per lane
+    constexpr int TPK = TP / OG;             // points per tile
+    using JCk = JetChunk<O0, O1, FIRST, NT8, TPK>;
     constexpr int CS = JCk::CS;
     extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
+    // FP32: KI*nb rows of NS floats; BF16: KI*(nb-1) pair rows of NS words (x2 for S = 3)
+    const int wrows = S == 0 ? nb : nb - 1;
     float *sW = smem;
-    float *sZ = smem + KI * nb * NS;
+    unsigned int *sP = reinterpret_cast<unsigned int *>(smem);
+    unsigned int *sPl = sP + KI * wrows * NS;
+    float *sZ = smem + KI * wrows * NS * (S == 3 ? 2 : 1);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int bl = lane >> 2, s = lane & 3;
-    const int pt = wv * PW + bl;
-    const int64_t ntiles = (n + TP - 1) / TP;
+    const int og = wv % OG, pt = (wv / OG) * PW + bl;
+    const int col0 = og * 4 * NQW + s * NQW;   // this lane's first output
+    const int64_t ntiles = (n + TPK - 1) / TPK;
     const int njc = (win + KJ - 1) / KJ;
     const bool single = KI >= win;
+    auto stage = [&](int i0, int nin) {
+        if constexpr (S == 0) {
+            stage_rows<NT8>(sW, W, i0 * nb, nin * nb, N, NS);
+        } else {
+            stage_pairs<NT8, false>(sP, W, i0, nin, nb, N, NS);
+            if constexpr (S == 3) stage_pairs<NT8, true>(sPl, W, i0, nin, nb, N, NS);
+        }
+    };
     JCk::zero_rows(sZ);
-    if (single) stage_rows<NT8>(sW, W, 0, win * nb, N, NS);
+    if (single) stage(0, win);
 
     // this lane's channel rows: coefficient sources (offsets in a staged input)
     float a0[RG];
@@ -198,27 +307,27 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_fwd_bs(const flo
     for (int r = 0; r < RG; ++r) {
         int s1, s2;
         channel_sources<O0, O1>(4 * r + s, a0[r], s1, s2);
-        off1[r] = s1 * TP + pt;
-        off2[r] = s2 * TP + pt;
+        off1[r] = s1 * TPK + pt;
+        off2[r] = s2 * TPK + pt;
     }
 
     JCk pre;
     int64_t tile = blockIdx.x;
     int jc = 0;
     if (tile < ntiles) pre.load(zin, n, win, tile, 0);
-    f4 acc[RG][NQ];
+    f4 acc[RG][NQW];
     while (tile < ntiles) {
         if (jc == 0) {
 #pragma unroll
             for (int r = 0; r < RG; ++r)
 #pragma unroll
-                for (int k = 0; k < NQ; ++k) acc[r][k] = (f4){0.f, 0.f, 0.f, 0.f};
+                for (int k = 0; k < NQW; ++k) acc[r][k] = (f4){0.f, 0.f, 0.f, 0.f};
         }
         const int ib = jc * KJ;
         const int iW = single ? 0 : (ib / KI) * KI;
         __syncthreads();
         pre.store(sZ);
-        if (!single && ib % KI == 0) stage_rows<NT8>(sW, W, iW * nb, min(KI, win - iW) * nb, N, NS);
+        if (!single && ib % KI == 0) stage(iW, min(KI, win - iW));
         __syncthreads();
         const int64_t cur_tile = tile;
         if (++jc == njc) {
@@ -246,37 +355,74 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_fwd_bs(const flo
                 const float x2 = zc[off2[r]];
                 a2[r] = x2 * x2;
             }
-            const float *wr = sW + ((i - iW) * nb + qa) * NS + s * NQ;
+            if constexpr (S == 0) {
+                const float *wr = sW + ((i - iW) * nb + qa) * NS + col0;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                float bw[NQ];
+                for (int t = 0; t < 4; ++t) {
+                    float bw[NQW];
 #pragma unroll
-                for (int k4 = 0; k4 < NQ / 4; ++k4) {
-                    const f4 w4 = *reinterpret_cast<const f4 *>(wr + t * NS + 4 * k4);
-                    bw[4 * k4 + 0] = w4[0];
-                    bw[4 * k4 + 1] = w4[1];
-                    bw[4 * k4 + 2] = w4[2];
-                    bw[4 * k4 + 3] = w4[3];
+                    for (int k4 = 0; k4 < NQW / 4; ++k4) {
+                        const f4 w4 = *reinterpret_cast<const f4 *>(wr + t * NS + 4 * k4);
+                        bw[4 * k4 + 0] = w4[0];
+                        bw[4 * k4 + 1] = w4[1];
+                        bw[4 * k4 + 2] = w4[2];
+                        bw[4 * k4 + 3] = w4[3];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RG; ++r) {
+                        const float A = a0[r] * vt[t][0] + a1[r] * vt[t][1] + a2[r] * vt[t][2];
+#pragma unroll
+                        for (int k = 0; k < NQW; ++k)
+                            acc[r][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(A, bw[k], acc[r][k], 0, 0, 0);
+                    }
                 }
+            } else {
+                // A operand: this lane's channel row over the 4 window rows
+                s4 ah[RG], al[RG];
 #pragma unroll
                 for (int r = 0; r < RG; ++r) {
-                    const float A = a0[r] * vt[t][0] + a1[r] * vt[t][1] + a2[r] * vt[t][2];
+                    float At[4];
 #pragma unroll
-                    for (int k = 0; k < NQ; ++k)
-                        acc[r][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(A, bw[k], acc[r][k], 0, 0, 0);
+                    for (int t = 0; t < 4; ++t) At[t] = a0[r] * vt[t][0] + a1[r] * vt[t][1] + a2[r] * vt[t][2];
+                    if constexpr (S >= 2)
+                        split4(At, ah[r], al[r]);
+                    else
+                        ah[r] = hi4(At);
+                }
+                const int prow = ((i - iW) * (nb - 1) + qa) * NS + col0;
+#pragma unroll
+                for (int k4 = 0; k4 < NQW / 4; ++k4) {
+                    const u4 p01 = *reinterpret_cast<const u4 *>(sP + prow + 4 * k4);
+                    const u4 p23 = *reinterpret_cast<const u4 *>(sP + prow + 2 * NS + 4 * k4);
+                    u4 q01, q23;
+                    if constexpr (S == 3) {
+                        q01 = *reinterpret_cast<const u4 *>(sPl + prow + 4 * k4);
+                        q23 = *reinterpret_cast<const u4 *>(sPl + prow + 2 * NS + 4 * k4);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int k = 4 * k4 + e;
+                        const s4 bh = mk4(p01[e], p23[e]);
+#pragma unroll
+                        for (int r = 0; r < RG; ++r) {
+                            acc[r][k] = mfma_bf16(ah[r], bh, acc[r][k]);
+                            if constexpr (S >= 2) acc[r][k] = mfma_bf16(al[r], bh, acc[r][k]);
+                            if constexpr (S == 3) acc[r][k] = mfma_bf16(ah[r], mk4(q01[e], q23[e]), acc[r][k]);
+                        }
+                    }
                 }
             }
         }
-        const int64_t p = cur_tile * TP + pt;
+        const int64_t p = cur_tile * TPK + pt;
         if (jc == 0 && p < n) {                 // the tile is complete
 #pragma unroll
             for (int r = 0; r < RG; ++r)
 #pragma unroll
-                for (int k = 0; k < NQ; ++k)
+                for (int k = 0; k < NQW; ++k)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int c = 4 * r + e;
-                        if (c < C) zout[(int64_t)(c * N + s * NQ + k) * n + p] = acc[r][k][e];
+                        if (c < C) zout[(int64_t)(c * N + col0 + k) * n + p] = acc[r][k][e];
                     }
         }
     }
@@ -285,11 +431,14 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_fwd_bs(const flo
 // ---------------------------------------------------------------------------
 // input bars: Ab_c(p,i,t) = sum_j W[i*nb + qa + t][j] * ybar[c][j][p]; then
 // the adjoint of the features through v..v''' gives zbar[.][i][p].
-// Block row = channel, block column = window row t. Even and odd output
-// quads accumulate in separate chains so consecutive MFMAs are independent.
+// Block row = channel, block column = window row t. S = 0: FP32, K = one
+// output per 4x4x1 MFMA; S > 0: BF16, K = 4 outputs per 4x4x4 MFMA, the
+// bars split once per tile and the weights staged as BF16 rows. Even and odd
+// output quads accumulate in separate chains so consecutive MFMAs are
+// independent.
 // ---------------------------------------------------------------------------
-template <int O0, int O1, int NQ>
-__global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const float *__restrict__ zin,
+template <int O0, int O1, int NQ, int S>
+__global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const float *__restrict__ zin,
                                                   const float *__restrict__ ybar,
                                                   const float *__restrict__ W,
                                                   float *__restrict__ zbar, int64_t n, int win,
@@ -298,41 +447,73 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const floa
     constexpr int C = Ch<O0, O1>::C;
     constexpr int RG = (C + 3) / 4;
     constexpr int N = 4 * NQ;
-    constexpr int NS = N + 4;
-    using JCk = JetChunk<O0, O1, false, NT8>;
+    constexpr int NS = N + 4;                // FP32 row stride (floats)
+    constexpr int NSH = N + 8;               // BF16 row stride (halfwords)
+    constexpr int SA = S >= 2 ? 2 : 1;       // pieces of the bar operand
+    constexpr int OG = NQ / 8;               // output groups: the waves split the outputs
+    constexpr int NQW = NQ / OG;             // output quads per wave
+    constexpr int TPK = TP / OG;             // points per tile
+    using JCk = JetChunk<O0, O1, false, NT8, TPK>;
     constexpr int CS = JCk::CS;
     extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     float *sW = smem;
-    float *sZ = smem + KI * nb * NS;
+    unsigned short *sH = reinterpret_cast<unsigned short *>(smem);
+    unsigned short *sHl = sH + KI * nb * NSH;
+    const int wfloats = S == 0 ? KI * nb * NS : KI * nb * NSH / 2 * (S == 3 ? 2 : 1);
+    float *sZ = smem + wfloats;
+    float *sRed = sZ + KJ * CS;              // [OG][KJ][C][TPK] partial input bars (OG > 1)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int bl = lane >> 2, s = lane & 3;
-    const int pt = wv * PW + bl;
-    const int64_t ntiles = (n + TP - 1) / TP;
+    const int og = wv % OG, pt = (wv / OG) * PW + bl;
+    const int jb = og * 4 * NQW;             // this wave's first output
+    const int64_t ntiles = (n + TPK - 1) / TPK;
     const int njc = (win + KJ - 1) / KJ;
     const bool single = KI >= win;
-    if (single) stage_rows<NT8>(sW, W, 0, win * nb, N, NS);
+    auto stage = [&](int i0, int nin) {
+        if constexpr (S == 0) {
+            stage_rows<NT8>(sW, W, i0 * nb, nin * nb, N, NS);
+        } else {
+            stage_rows_bf16<NT8, false>(sH, W, i0 * nb, nin * nb, N, NSH);
+            if constexpr (S == 3) stage_rows_bf16<NT8, true>(sHl, W, i0 * nb, nin * nb, N, NSH);
+        }
+    };
+    if (single) stage(0, win);
 
     JCk pre;
     int64_t tile = blockIdx.x;
     int jc = 0;
     if (tile < ntiles) pre.load(zin, n, win, tile, 0);
-    float yb[RG][N];
+    // the output bars of this lane's channel rows: FP32 (S = 0) or BF16 pieces
+    float yb[S == 0 ? RG : 1][S == 0 ? 4 * NQW : 1];
+    s4 ybp[S == 0 ? 1 : RG][S == 0 ? 1 : NQW][SA];
     while (tile < ntiles) {
-        const int64_t p = tile * TP + pt;
+        const int64_t cur_tile = tile;
+        const int64_t p = cur_tile * TPK + pt;
         const bool ok = p < n;
         if (jc == 0) {
-            // the output bars of this lane's channel rows, all N outputs
             const int64_t pc = ok ? p : 0;
 #pragma unroll
             for (int r = 0; r < RG; ++r) {
                 const int c = 4 * r + s;
                 const int cc = c < C ? c : 0;
 #pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    const float y = ybar[(int64_t)(cc * N + j) * n + pc];
-                    yb[r][j] = (ok && c < C) ? y : 0.f;
+                for (int j4 = 0; j4 < NQW; ++j4) {
+                    float y[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float v = ybar[(int64_t)(cc * N + jb + 4 * j4 + e) * n + pc];
+                        y[e] = (ok && c < C) ? v : 0.f;
+                    }
+                    if constexpr (S == 0) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) yb[r][4 * j4 + e] = y[e];
+                    } else if constexpr (SA == 2) {
+                        split4(y, ybp[r][j4][0], ybp[r][j4][1]);
+                    } else {
+                        ybp[r][j4][0] = hi4(y);
+                    }
                 }
             }
         }
@@ -340,7 +521,7 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const floa
         const int iW = single ? 0 : (ib / KI) * KI;
         __syncthreads();
         pre.store(sZ);
-        if (!single && ib % KI == 0) stage_rows<NT8>(sW, W, iW * nb, min(KI, win - iW) * nb, N, NS);
+        if (!single && ib % KI == 0) stage(iW, min(KI, win - iW));
         __syncthreads();
         if (++jc == njc) {
             jc = 0;
@@ -353,25 +534,43 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const floa
             const float *zc = sZ + (i - ib) * CS + pt;
             float zj[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) zj[c] = zc[c * TP];
+            for (int c = 0; c < C; ++c) zj[c] = zc[c * TPK];
             const float zt = zj[0] * inv_w + zoff;
             const int qa = window_k3(zt, nb);
-            // this lane (column t = s) reads window row qa + s
-            const float *wr = sW + ((i - iW) * nb + qa + s) * NS;
             f4 ab[2][RG];       // two accumulation chains: even / odd output quads
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int r = 0; r < RG; ++r) ab[h][r] = (f4){0.f, 0.f, 0.f, 0.f};
+            if constexpr (S == 0) {
+                // this lane (column t = s) reads window row qa + s
+                const float *wr = sW + ((i - iW) * nb + qa + s) * NS + jb;
 #pragma unroll
-            for (int j4 = 0; j4 < NQ; ++j4) {
-                const f4 w4 = *reinterpret_cast<const f4 *>(wr + 4 * j4);
+                for (int j4 = 0; j4 < NQW; ++j4) {
+                    const f4 w4 = *reinterpret_cast<const f4 *>(wr + 4 * j4);
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
+                    for (int e = 0; e < 4; ++e)
 #pragma unroll
-                    for (int r = 0; r < RG; ++r)
-                        ab[j4 & 1][r] = __builtin_amdgcn_mfma_f32_4x4x1f32(yb[r][4 * j4 + e], w4[e],
-                                                                           ab[j4 & 1][r], 0, 0, 0);
+                        for (int r = 0; r < RG; ++r)
+                            ab[j4 & 1][r] = __builtin_amdgcn_mfma_f32_4x4x1f32(yb[r][4 * j4 + e], w4[e],
+                                                                               ab[j4 & 1][r], 0, 0, 0);
+                }
+            } else {
+                const int hrow = ((i - iW) * nb + qa + s) * NSH + jb;
+#pragma unroll
+                for (int j4 = 0; j4 < NQW; ++j4) {
+                    const s4 wh = __builtin_bit_cast(s4, *reinterpret_cast<const u2 *>(sH + hrow + 4 * j4));
+                    s4 wl;
+                    if constexpr (S == 3)
+                        wl = __builtin_bit_cast(s4, *reinterpret_cast<const u2 *>(sHl + hrow + 4 * j4));
+#pragma unroll
+                    for (int r = 0; r < RG; ++r) {
+                        f4 &a = ab[j4 & 1][r];
+                        a = mfma_bf16(ybp[r][j4][0], wh, a);
+                        if constexpr (S >= 2) a = mfma_bf16(ybp[r][j4][SA - 1], wh, a);
+                        if constexpr (S == 3) a = mfma_bf16(ybp[r][j4][0], wl, a);
+                    }
+                }
             }
             // lane (block, t): ab[.][r][e] = Abar of channel 4r+e for row t = s
             float v[4];
@@ -385,15 +584,34 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const floa
             features_adjoint<float, O0, O1>(v, zj, Ab, zb);
 #pragma unroll
             for (int c = 0; c < C; ++c) zb[c] = quad_sum(zb[c]);
-            if (ok) {
+            if constexpr (OG == 1) {
+                if (ok) {
 #pragma unroll
-                for (int r = 0; r < RG; ++r) {
-                    const int c = 4 * r + s;
-                    float val = zb[0];
+                    for (int r = 0; r < RG; ++r) {
+                        const int c = 4 * r + s;
+                        float val = zb[0];
 #pragma unroll
-                    for (int cc = 1; cc < C; ++cc) val = (c == cc) ? zb[cc] : val;
-                    if (c < C) zbar[(int64_t)(c * win + i) * n + p] = val;
+                        for (int cc = 1; cc < C; ++cc) val = (c == cc) ? zb[cc] : val;
+                        if (c < C) zbar[(int64_t)(c * win + i) * n + p] = val;
+                    }
                 }
+            } else if (s == 0) {
+                // this wave's part of the sum over outputs; the groups are
+                // added in order once the chunk is done
+#pragma unroll
+                for (int c = 0; c < C; ++c) sRed[((og * KJ + (i - ib)) * C + c) * TPK + pt] = zb[c];
+            }
+        }
+        if constexpr (OG > 1) {
+            __syncthreads();
+            const int nin = ie - ib;
+            for (int e = threadIdx.x; e < nin * C * TPK; e += NT8) {
+                const int pp = e % TPK, c = (e / TPK) % C, il = e / (TPK * C);
+                const int64_t pq = cur_tile * TPK + pp;
+                float v = sRed[((0 * KJ + il) * C + c) * TPK + pp];
+#pragma unroll
+                for (int o = 1; o < OG; ++o) v += sRed[((o * KJ + il) * C + c) * TPK + pp];
+                if (pq < n) zbar[(int64_t)(c * win + ib + il) * n + pq] = v;
             }
         }
     }
@@ -418,7 +636,7 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1>())) void k_dx_bs(const floa
 // ---------------------------------------------------------------------------
 template <int NQ> constexpr int dw_pc() { return NQ >= 32 ? 8 : 16; }
 
-template <int O0, int O1, bool FIRST, int NQ, int II>
+template <int O0, int O1, bool FIRST, int NQ, int II, int S>
 __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
                                               const float *__restrict__ ybar,
                                               float *__restrict__ part, int64_t n, int win,
@@ -515,10 +733,43 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
             }
 #pragma unroll
         for (int q = 0; q < PASSES; ++q) d[q] = (f4){0.f, 0.f, 0.f, 0.f};
+        if constexpr (S == 0) {
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+            for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int q = 0; q < PASSES; ++q) d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[c], yv[q][c], d[q], 0, 0, 0);
+                for (int q = 0; q < PASSES; ++q)
+                    d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[c], yv[q][c], d[q], 0, 0, 0);
+        } else {
+            // K = 4 channels per 4x4x4 MFMA (channels beyond C are zero)
+            constexpr int CG = CP / 4;
+            s4 fh[CG], fl[CG];
+#pragma unroll
+            for (int g4 = 0; g4 < CG; ++g4) {
+                float a4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a4[e] = (4 * g4 + e < C) ? A[(4 * g4 + e) < C ? 4 * g4 + e : 0] : 0.f;
+                if constexpr (S >= 2)
+                    split4(a4, fh[g4], fl[g4]);
+                else
+                    fh[g4] = hi4(a4);
+            }
+#pragma unroll
+            for (int g4 = 0; g4 < CG; ++g4)
+#pragma unroll
+                for (int q = 0; q < PASSES; ++q) {
+                    float y4[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) y4[e] = (4 * g4 + e < C) ? yv[q][4 * g4 + e] : 0.f;
+                    s4 yh, yl;
+                    if constexpr (S == 3)
+                        split4(y4, yh, yl);
+                    else
+                        yh = hi4(y4);
+                    d[q] = mfma_bf16(fh[g4], yh, d[q]);
+                    if constexpr (S >= 2) d[q] = mfma_bf16(fl[g4], yh, d[q]);
+                    if constexpr (S == 3) d[q] = mfma_bf16(fh[g4], yl, d[q]);
+                }
+        }
         return qa;
     };
     // rows qa..qa+3 of this lane's input: all reads, then all writes
@@ -811,10 +1062,24 @@ static int grid_blocks(int64_t tiles, int cap) { return (int)std::max<int64_t>(1
 
 // inputs whose weight rows are staged at once (a multiple of KJ, or all of
 // them), and the LDS bytes of those rows plus one chunk of jets
-static void w_stage(LayerShape ls, int C, int &KI, size_t &bytes)
+// Inputs whose weight rows are staged at once (a multiple of KJ, or all of
+// them), and the LDS bytes of those rows plus one chunk of jets. Forward
+// BF16 stages nb-1 row pairs of N+4 words per input, input-bar BF16 nb rows
+// of N+8 halfwords, FP32 nb rows of N+4 floats; S = 3 stages the low
+// pieces as well.
+static void w_stage(LayerShape ls, int C, int S, bool fwd, int &KI, size_t &bytes)
 {
-    const size_t per_in = (size_t)ls.nb * (ls.wout + 4) * sizeof(float);
-    const size_t jets = (size_t)KJ * (C + 1) * TP * sizeof(float);
+    size_t per_in;
+    if (S == 0)
+        per_in = (size_t)ls.nb * (ls.wout + 4) * sizeof(float);
+    else if (fwd)
+        per_in = (size_t)(ls.nb - 1) * (ls.wout + 4) * sizeof(unsigned int);
+    else
+        per_in = (size_t)ls.nb * (ls.wout + 8) * sizeof(unsigned short);
+    if (S == 3) per_in *= 2;
+    const int og = ls.wout / 32;                    // output groups (tiles of 128/og points)
+    size_t jets = (size_t)KJ * (C + 1) * (TP / og) * sizeof(float);
+    if (!fwd && og > 1) jets += (size_t)og * KJ * C * (TP / og) * sizeof(float);
     size_t ki = (LDS_FWD - jets) / per_in;
     if (ki >= (size_t)ls.win)
         ki = ls.win;
@@ -824,8 +1089,35 @@ static void w_stage(LayerShape ls, int C, int &KI, size_t &bytes)
     bytes = per_in * ki + jets;
 }
 
+// BF16 kernels are built for the channel sets of the PDE residuals (Poisson,
+// Burgers) and of boundary values.
+#define HRK_CH_SWITCH_BF(ch, ...)                                 \
+    switch ((ch).o0 * 3 + (ch).o1) {                              \
+    case 0: { constexpr int O0 = 0, O1 = 0; __VA_ARGS__; } break; \
+    case 7: { constexpr int O0 = 2, O1 = 1; __VA_ARGS__; } break; \
+    case 8: { constexpr int O0 = 2, O1 = 2; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                         \
+    }
+
+#define HRK_S_SWITCH(S_, ...)                                     \
+    switch (S_) {                                                 \
+    case 1: { constexpr int S = 1; __VA_ARGS__; } break;          \
+    case 2: { constexpr int S = 2; __VA_ARGS__; } break;          \
+    case 3: { constexpr int S = 3; __VA_ARGS__; } break;          \
+    default: return hipErrorInvalidValue;                         \
+    }
+
+// FP32 (S = 0) over every channel set, BF16 (S = 1..3) over HRK_CH_SWITCH_BF's
+#define HRK_CH_S_SWITCH(ch, S_, ...)                                                          \
+    if ((S_) == 0) {                                                                          \
+        HRK_CH_SWITCH32(ch, { constexpr int S = 0; __VA_ARGS__; });                           \
+    } else {                                                                                  \
+        HRK_CH_SWITCH_BF(ch, { HRK_S_SWITCH(S_, __VA_ARGS__); });                             \
+    }
+
 hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float *W, float *zout,
-                           int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, hipStream_t st)
+                           int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, int S,
+                           hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     if (ls.wout == 1) {
@@ -837,16 +1129,17 @@ hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float
     }
     int KI;
     size_t sh;
-    w_stage(ls, ch.C(), KI, sh);
-    const int grid = grid_blocks((n + TP - 1) / TP, cu_blocks);
-    HRK_CH_SWITCH32(ch, {
+    w_stage(ls, ch.C(), S, true, KI, sh);
+    const int tpk = TP / (ls.wout / 32);
+    const int grid = grid_blocks((n + tpk - 1) / tpk, cu_blocks);
+    HRK_CH_S_SWITCH(ch, S, {
         HRK_NQ_SWITCH(ls.wout, {
             if (first) {
-                auto kf = k_fwd_bs<O0, O1, true, NQ>;
+                auto kf = k_fwd_bs<O0, O1, true, NQ, S>;
                 set_lds_limit((const void *)kf);
                 kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
             } else {
-                auto kf = k_fwd_bs<O0, O1, false, NQ>;
+                auto kf = k_fwd_bs<O0, O1, false, NQ, S>;
                 set_lds_limit((const void *)kf);
                 kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
             }
@@ -856,7 +1149,8 @@ hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float
 }
 
 hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const float *W, float *zbar,
-                          int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, hipStream_t st)
+                          int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, int S,
+                          hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     if (ls.wout == 1) {
@@ -868,11 +1162,12 @@ hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const
     }
     int KI;
     size_t sh;
-    w_stage(ls, ch.C(), KI, sh);
-    const int grid = grid_blocks((n + TP - 1) / TP, cu_blocks);
-    HRK_CH_SWITCH32(ch, {
+    w_stage(ls, ch.C(), S, false, KI, sh);
+    const int tpk = TP / (ls.wout / 32);
+    const int grid = grid_blocks((n + tpk - 1) / tpk, cu_blocks);
+    HRK_CH_S_SWITCH(ch, S, {
         HRK_NQ_SWITCH(ls.wout, {
-            auto kf = k_dx_bs<O0, O1, NQ>;
+            auto kf = k_dx_bs<O0, O1, NQ, S>;
             set_lds_limit((const void *)kf);
             kf<<<grid, NT8, sh, st>>>(zin, ybar, W, zbar, n, ls.win, KI, g);
         });
@@ -914,7 +1209,7 @@ int dw_bs32_splits(int64_t n, LayerShape ls)
 }
 
 hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float *ybar, float *part,
-                          int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, hipStream_t st)
+                          int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, int S, hipStream_t st)
 {
     if (ls.wout == 1) {
         dim3 grid((unsigned)((ls.win + NT / DL_SL - 1) / (NT / DL_SL)), (unsigned)nsplit);
@@ -928,17 +1223,17 @@ hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float 
     const int ibe = tl.II * tl.WI;
     const dim3 grid((unsigned)((ls.win + ibe - 1) / ibe), (unsigned)nsplit);
     const int wi = tl.WI;
-    HRK_CH_SWITCH32(ch, {
+    HRK_CH_S_SWITCH(ch, S, {
         HRK_NQ_SWITCH(ls.wout, {
             HRK_II_SWITCH(tl.II, {
                 if constexpr (16 / II <= NQ) {
                     const size_t sh = dw_bs_lds(ch.C(), ls.nb, ls.wout, II);
                     if (first) {
-                        auto kf = k_dw_bs<O0, O1, true, NQ, II>;
+                        auto kf = k_dw_bs<O0, O1, true, NQ, II, S>;
                         set_lds_limit((const void *)kf);
                         kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g);
                     } else {
-                        auto kf = k_dw_bs<O0, O1, false, NQ, II>;
+                        auto kf = k_dw_bs<O0, O1, false, NQ, II, S>;
                         set_lds_limit((const void *)kf);
                         kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g);
                     }

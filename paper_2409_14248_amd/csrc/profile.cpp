@@ -21,11 +21,12 @@ std::vector<Rec> g_recs;
 
 bool prof_on() { return g_on; }
 
-ProfScope::ProfScope(const char *name, int layer, hipStream_t st) : st_(st), idx_(-1)
+ProfScope::ProfScope(const char *name, int layer, hipStream_t st, bool bc) : st_(st), idx_(-1)
 {
     if (!g_on) return;
     Rec r;
     r.name = layer >= 0 ? std::string(name) + "_l" + std::to_string(layer) : std::string(name);
+    if (bc) r.name += "_bc";
     if (hipEventCreate(&r.a) != hipSuccess) return;
     if (hipEventCreate(&r.b) != hipSuccess) {
         (void)hipEventDestroy(r.a);

@@ -76,6 +76,14 @@ int check_net(const hrkan_net_desc *d, NetInfo *ni)
     ni->elem = d->dtype == HRKAN_F64 ? 8 : 4;
     ni->maxw = maxw;
     if (ni->nb > 32) return fail(HRKAN_ERR_UNSUPPORTED, "n_b = G + k = %d > 32", ni->nb);
+    if (d->dtype == HRKAN_BF16) {
+        if (d->k != 3 || d->m != 4)
+            return fail(HRKAN_ERR_UNSUPPORTED, "HRKAN_BF16 needs k = 3 and m = 4 (k=%d, m=%d)", d->k, d->m);
+        for (int l = 0; l < d->n_layers; ++l)
+            if (!bs32_supported(LayerShape{d->widths[l], d->widths[l + 1], ni->nb}))
+                return fail(HRKAN_ERR_UNSUPPORTED, "HRKAN_BF16: layer %d shape %d x %d (n_b %d) not supported",
+                            l, d->widths[l], d->widths[l + 1], ni->nb);
+    }
     ni->n_params = 0;
     for (int l = 0; l < ni->L; ++l) ni->n_params += (int64_t)ni->w[l] * ni->nb * ni->w[l + 1];
     return HRKAN_OK;
@@ -130,6 +138,10 @@ bool use_bs32(const NetInfo &ni, int l)
     return ni.dtype != HRKAN_F64 && ni.m == 4 && ni.k == 3 &&
            bs32_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb});
 }
+
+// BF16 product terms of the matrix-core kernels (0: FP32 products). check_net
+// admits HRKAN_BF16 only where every layer runs on them.
+int bf16_terms(const NetInfo &ni) { return ni.dtype == HRKAN_BF16 ? ni.S : 0; }
 
 int dw_splits(const NetInfo &ni, int l, int64_t n)
 {
@@ -260,7 +272,7 @@ namespace {
 
 template <typename T>
 int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, int64_t n,
-                 T *jets_out, T *saved, T *tmp0, T *tmp1, hipStream_t st)
+                 T *jets_out, T *saved, T *tmp0, T *tmp1, hipStream_t st, bool bc = false)
 {
     const GridP<T> g = make_grid<T>(ni);
     const int C = ch.C();
@@ -277,11 +289,11 @@ int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, i
             zout = (l % 2 == 0) ? tmp0 : tmp1;
         hipError_t e;
         {
-            ProfScope ps("fwd", l, st);
+            ProfScope ps("fwd", l, st, bc);
             const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
             if constexpr (std::is_same<T, float>::value) {
                 if (use_bs32(ni, l))
-                    e = launch_fwd_bs32(ch, l == 0, zin, W[l], zout, n, ls, g, cu_blocks(), st);
+                    e = launch_fwd_bs32(ch, l == 0, zin, W[l], zout, n, ls, g, cu_blocks(), bf16_terms(ni), st);
                 else
                     e = launch_fwd_generic<T>(ch, l == 0, zin, W[l], zout, n, ls, g, st);
             } else {
@@ -329,7 +341,7 @@ struct RevSet {
 
 template <typename T>
 int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const int64_t *off, T *part,
-                hipStream_t st)
+                hipStream_t st, bool bc)
 {
     const GridP<T> g = make_grid<T>(ni);
     const T *ybar = S.seed;
@@ -339,11 +351,11 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
         const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
         hipError_t e;
         {
-            ProfScope ps("dw", l, st);
+            ProfScope ps("dw", l, st, bc);
             T *dst = part + off[l];
             if constexpr (std::is_same<T, float>::value) {
                 if (use_bs32(ni, l))
-                    e = launch_dw_bs32(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, st);
+                    e = launch_dw_bs32(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, bf16_terms(ni), st);
                 else
                     e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, st);
             } else {
@@ -354,10 +366,10 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
         if (l == 0) break;
         T *zbar = (ybar == S.bar0) ? S.bar1 : S.bar0;
         {
-            ProfScope ps("dx", l, st);
+            ProfScope ps("dx", l, st, bc);
             if constexpr (std::is_same<T, float>::value) {
                 if (use_bs32(ni, l))
-                    e = launch_dx_bs32(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, cu_blocks(), st);
+                    e = launch_dx_bs32(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, cu_blocks(), bf16_terms(ni), st);
                 else
                     e = launch_dx_generic<T>(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, st);
             } else {
@@ -393,8 +405,8 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
     }
     const bool split = fk && n0 > 0 && n1 > 0;
     if (split) TRY(fork_to(fk, st));
-    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st));
-    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st));
+    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st, true));
+    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false));
     if (split) TRY(join_from(fk, st));
     for (int l = ni.L - 1; l >= 0; --l) {
         const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
@@ -520,7 +532,7 @@ int hrkan_workspace_bytes(const hrkan_net_desc *net, const hrkan_pde_desc *pde, 
     TRY(check_pde(pde));
     if (n_int < 0 || n_bc < 0) return fail(HRKAN_ERR_INVALID_ARG, "negative point count");
     if (!bytes) return fail(HRKAN_ERR_INVALID_ARG, "bytes is NULL");
-    *bytes = extra_ws_bytes(ni, n_int, n_bc) + layout(ni, n_int, n_bc).total;
+    *bytes = layout(ni, n_int, n_bc).total;
     return HRKAN_OK;
 }
 
@@ -544,9 +556,6 @@ int hrkan_forward_jets(const hrkan_net_desc *net, const void *const *W, const vo
         return forward_impl<double>(ni, ch, (const double *const *)W, (const double *)x, n,
                                     (double *)jets_out, (double *)saved, (double *)(w + L.bars0),
                                     (double *)(w + L.bars1), stream);
-    if (ni.dtype == HRKAN_BF16)
-        return bf16_forward(ni, ch, W, (const float *)x, n, (float *)jets_out, (float *)saved, ws,
-                            ws_bytes, stream);
     return forward_impl<float>(ni, ch, (const float *const *)W, (const float *)x, n,
                                (float *)jets_out, (float *)saved, (float *)(w + L.bars0),
                                (float *)(w + L.bars1), stream);
@@ -612,10 +621,6 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
         return reverse_impl<double>(ni, (const double *const *)W, &s, 1, (double *const *)gW_out,
                                     accumulate, (double *)(w + L.part), stream, nullptr);
     }
-    if (ni.dtype == HRKAN_BF16)
-        return bf16_backward(ni, ch, W, (const float *)x, n, (const float *)seed,
-                             (const float *)saved, (float *const *)gW_out, accumulate, ws, ws_bytes,
-                             stream);
     RevSet<float> s{ch, (const float *)x, n, (const float *)seed, (const float *)saved,
                     (float *)(w + L.bars0), (float *)(w + L.bars1)};
     return reverse_impl<float>(ni, (const float *const *)W, &s, 1, (float *const *)gW_out, accumulate,
@@ -641,7 +646,6 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
     size_t need = 0;
     TRY(hrkan_workspace_bytes(net, pde, pts->n_int, pts->n_bc, &need));
     TRY(check_ws(ws, ws_bytes, need));
-    if (ni.dtype == HRKAN_BF16) return bf16_step(ni, pde, W, pts, loss_out, gW_out, ws, ws_bytes, stream);
     const WsLayout L = layout(ni, pts->n_int, pts->n_bc);
     char *w = (char *)ws;
     ChanCfg chi, chb;
@@ -661,7 +665,7 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         if (fk) TRY(fork_to(fk, stream));
         if (nb_ > 0)
             TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
-                                nullptr, nullptr, fk ? fk->side : stream));
+                                nullptr, nullptr, fk ? fk->side : stream, true));
         if (ni_ > 0)
             TRY(forward_impl<T>(ni, chi, (const T *const *)W, (const T *)pts->x_int, ni_, jets, sv_int,
                                 nullptr, nullptr, stream));

@@ -49,13 +49,15 @@ int get_fork(hipStream_t st, Fork **out);
 int fork_to(Fork *f, hipStream_t st);      // side waits for st's work so far
 int join_from(Fork *f, hipStream_t st);    // st waits for side's work so far
 bool use_bs32(const NetInfo &ni, int l);
+int bf16_terms(const NetInfo &ni);
 int cu_blocks();
 WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc);
 
 // Brackets one kernel launch with HIP events while profiling is enabled.
 class ProfScope {
   public:
-    ProfScope(const char *name, int layer, hipStream_t st);
+    // name_l<layer>, with a _bc suffix for the boundary point set (bc = true)
+    ProfScope(const char *name, int layer, hipStream_t st, bool bc = false);
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;
@@ -66,17 +68,6 @@ class ProfScope {
 };
 bool prof_on();
 
-// Workspace beyond `layout` needed by the BF16 path (packed weights).
-size_t extra_ws_bytes(const NetInfo &ni, int64_t n_int, int64_t n_bc);
 
-// BF16 path (matrix-core contractions, FP32 jets).
-int bf16_forward(const NetInfo &ni, ChanCfg ch, const void *const *W, const float *x, int64_t n,
-                 float *jets_out, float *saved, void *ws, size_t ws_bytes, hipStream_t st);
-int bf16_backward(const NetInfo &ni, ChanCfg ch, const void *const *W, const float *x, int64_t n,
-                  const float *seed, const float *saved, float *const *gW, int accumulate, void *ws,
-                  size_t ws_bytes, hipStream_t st);
-int bf16_step(const NetInfo &ni, const hrkan_pde_desc *pde, const void *const *W,
-              const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
-              size_t ws_bytes, hipStream_t st);
 
 }  // namespace hrk

@@ -79,6 +79,10 @@ def test_bad_masks(mask, code):
     (lambda d: setattr(d, "dtype", 7), H.ERR_INVALID_ARG),
     (lambda d: (setattr(d, "dtype", H.BF16), setattr(d, "bf16_split", 4)), H.ERR_INVALID_ARG),
     (lambda d: setattr(d, "G", 40), H.ERR_UNSUPPORTED),
+    # BF16 runs only on the matrix-core kernels: k = 3, m = 4, hidden widths 32/64/128
+    (lambda d: (setattr(d, "dtype", H.BF16), setattr(d, "bf16_split", 1)), H.ERR_UNSUPPORTED),
+    (lambda d: (setattr(d, "dtype", H.BF16), d.widths.__setitem__(1, 32), setattr(d, "m", 2)),
+     H.ERR_UNSUPPORTED),
 ])
 def test_invalid_net_rejected(mutate, code):
     nd = nd_of()
@@ -88,6 +92,15 @@ def test_invalid_net_rejected(mutate, code):
     rc = H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(pd), 10, 10, ctypes.byref(b))
     assert rc == code, H.lib().hrkan_last_error()
     assert H.lib().hrkan_last_error().decode() != ""
+
+
+def test_bf16_net_of_supported_shape_accepted():
+    nd = nd_of((2, 32, 32, 1), G=10)
+    nd.dtype, nd.bf16_split = H.BF16, 3
+    b = ctypes.c_size_t(0)
+    pd = H.pde_desc(WL.Pde(WL.BURGERS1D))
+    assert H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(pd), 10, 10, ctypes.byref(b)) == H.OK
+    assert b.value > 0
 
 
 def test_workspace_grows_with_points_and_saved_bytes():

@@ -1,0 +1,100 @@
+"""Parity of the BF16 matrix-core path (HRKAN_BF16, bf16_split S = 1, 2, 3)
+with the FP64 oracle.
+
+Jets, bars and accumulation stay FP32; each basis-by-W product (and each
+feature-by-bar product of the weight gradient) is taken as S BF16 products.
+Gate (normwise relative error against the exact oracle on the same FP32
+inputs): max(2e-2, 3 x floor), the floor being the error of the oracle's
+BF16 rounding model -- features and bars split into S BF16 pieces, weights
+rounded to BF16 -- against the exact oracle: what BF16 storage alone costs
+on that network. S = 3 (a_hi b_hi + a_lo b_hi + a_hi b_lo) keeps about 16
+mantissa bits per product and is in addition held to the FP32 gates.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import relerr
+from gpu_util import SLOTS_OF_MASK, gpu_step, oracle_step, to_dev
+from paper_2409_14248_amd import hrkan as H
+from paper_2409_14248_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-2
+FLOOR_FACTOR = 3.0
+
+
+def bf16_round(a):
+    """Round-to-nearest-even of FP32 values to the BF16 grid (as float64)."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_floor_step(pr, S):
+    """Exact oracle step and the relative errors of its BF16 rounding model
+    (weights rounded to BF16) for the loss and each weight gradient."""
+    q = pr.rounded(np.float32)
+    ref = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
+    Wb = [bf16_round(w) for w in q.W]
+    with O.rounding("bf16", min(S, 2)):
+        rnd = O.step(q.net, q.pde, Wb, q.x_int, q.x_bc, q.g_bc)
+    return ref, relerr(rnd["loss"], ref["loss"]), [relerr(a, b) for a, b in zip(rnd["gW"], ref["gW"])]
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_forward_jets_bf16_burgers_c2_net(S):
+    pr = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=4096 + 37, n_bc=0)
+    q = pr.rounded(np.float32)
+    nd = H.net_desc(pr.net, "bf16", S)
+    pd = H.pde_desc(pr.pde)
+    W = [to_dev(w, "f32") for w in pr.W]
+    ws = H.alloc_workspace(H.workspace_bytes(nd, pd, pr.n_int, 0))
+    jets = H.forward_jets(nd, W, to_dev(pr.x_int, "f32"), H.MASK_BURGERS, ws).double().cpu().numpy()
+    ref = O.forward(q.net, q.W, q.x_int)
+    with O.rounding("bf16", min(S, 2)):
+        rnd = O.forward(q.net, [bf16_round(w) for w in q.W], q.x_int)
+    for c, slot in enumerate(SLOTS_OF_MASK[H.MASK_BURGERS]):
+        floor = relerr(rnd[slot], ref[slot])
+        err = relerr(jets[c], ref[slot])
+        assert err <= max(TOL, FLOOR_FACTOR * floor), (S, c, err, floor)
+        if S == 3:
+            assert err <= 1e-4, (c, err)
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+@pytest.mark.parametrize("name", ["burgers_c2", "poisson_c3"])
+def test_step_bf16(name, S):
+    pr = WL.make_problem(WL.WORKLOADS[name], n_int=4096 + 37, n_bc=256)
+    loss, gW, ws = gpu_step(pr, "bf16", S)
+    ref, fl, fg = bf16_floor_step(pr, S)
+    assert H.read_status(ws) == 0
+    assert relerr(loss, ref["loss"]) <= max(TOL, FLOOR_FACTOR * fl), (loss, ref["loss"], fl)
+    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
+        assert relerr(a, b) <= max(TOL, FLOOR_FACTOR * fg[l]), (l, relerr(a, b), fg[l])
+    if S == 3 and name == "burgers_c2":
+        f32 = oracle_step(pr, "f32")
+        assert relerr(loss, f32["loss"]) <= 1e-4
+
+
+def test_step_bf16_s2_burgers_c4_net_bf16_weights():
+    """The [2,128,128,128,1], G = 20 network with weights already on the
+    BF16 grid: the oracle gets exactly the weights the matrix cores use."""
+    pr = WL.make_problem(WL.WORKLOADS["burgers_c4"], n_int=2048 + 11, n_bc=128)
+    pr = WL.Problem(pr.net, pr.pde, [bf16_round(w) for w in pr.W], pr.x_int, pr.x_bc, pr.g_bc)
+    loss, gW, _ = gpu_step(pr, "bf16", 2)
+    ref, fl, fg = bf16_floor_step(pr, 2)
+    assert relerr(loss, ref["loss"]) <= max(TOL, FLOOR_FACTOR * fl), (relerr(loss, ref["loss"]), fl)
+    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
+        assert relerr(a, b) <= max(TOL, FLOOR_FACTOR * fg[l]), (l, relerr(a, b), fg[l])
+
+
+def test_bf16_step_is_deterministic():
+    pr = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=5000, n_bc=300)
+    a_loss, a_gW, _ = gpu_step(pr, "bf16", 2)
+    b_loss, b_gW, _ = gpu_step(pr, "bf16", 2)
+    assert np.array_equal(a_loss, b_loss)
+    for a, b in zip(a_gW, b_gW):
+        assert np.array_equal(a, b)
