@@ -106,6 +106,8 @@ def main():
 
     wl = WL.WORKLOADS[args.workload]
     dtype = args.dtype or wl.dtype
+    if wl.n_instances > 1:
+        return bench_batched(args, wl)
     pr = WL.make_problem(wl)
     step = H.Step(pr, dtype, args.bf16_split)
     torch.cuda.synchronize()
@@ -214,6 +216,84 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 5) for k, v in sorted(prof.items())},
+    }
+    print(json.dumps(out))
+
+
+def bench_batched(args, wl):
+    """Batched instances: one plan (one HIP graph launch per step) against the
+    plain FP32 step called once per instance."""
+    import numpy as np
+    import torch
+
+    from paper_2409_14248_amd import hrkan as H
+    from paper_2409_14248_amd import workloads as WL
+
+    probs = WL.batched_instances(wl)
+    n_int = sum(p.n_int for p in probs)
+    n_bc = sum(p.n_bc for p in probs)
+    t0 = time.time()
+    plan = H.Plan(probs)
+    torch.cuda.synchronize()
+    create_s = time.time() - t0
+
+    def timed(fn, k):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    for _ in range(args.warmup):
+        plan.execute()
+    ms = timed(plan.execute, args.steps)
+
+    # the plain FP32 step, once per instance (eager launches, shared workspace)
+    nd = H.net_desc(probs[0].net, "f32")
+    ws = H.alloc_workspace(max(H.workspace_bytes(nd, H.pde_desc(p.pde), p.n_int, p.n_bc) for p in probs))
+    dev = [([torch.as_tensor(w, dtype=torch.float32, device="cuda") for w in p.W],
+            torch.as_tensor(p.x_int, dtype=torch.float32, device="cuda"),
+            torch.as_tensor(p.x_bc, dtype=torch.float32, device="cuda"),
+            torch.as_tensor(p.g_bc, dtype=torch.float32, device="cuda"), H.pde_desc(p.pde)) for p in probs]
+    loss = torch.empty(3, dtype=torch.float64, device="cuda")
+    gW = [torch.empty_like(w) for w in dev[0][0]]
+
+    def looped():
+        for W, xi, xb, g, pd in dev:
+            H.step(nd, pd, W, xi, xb, g, ws, loss_out=loss, gW_out=gW)
+
+    looped()
+    loop_ms = timed(looped, max(1, args.steps // 10))
+
+    f_pt = sum(v for v in layer_flops(probs[0].net, 4, 1).values())
+    f_bc = sum(v for v in layer_flops(probs[0].net, 1, 1).values())
+    step_flops = f_pt * n_int + f_bc * n_bc
+    achieved = step_flops / (ms * 1e-3) / 1e12
+    tp, blocks = plan.config()
+    out = {
+        "metric": METRIC,
+        "value": round(n_int / (ms * 1e-3), 1),
+        "unit": "points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "instances": len(probs), "widths": list(probs[0].net.widths),
+                   "G": probs[0].net.G, "n_int_total": n_int, "n_bc_total": n_bc,
+                   "tile_points": tp, "blocks": blocks},
+        "launch": "hip_graph (one per batched step)",
+        "plan_create_s": round(create_s, 2),
+        "looped_single_step_ms": round(loop_ms, 3),
+        "looped_points_per_s": round(n_int / (loop_ms * 1e-3), 1),
+        "speedup_vs_looped": round(loop_ms / ms, 3),
+        "roofline": {"bound": "mfma", "kernel": "whole batched step (one graph)", "achieved": round(achieved, 3),
+                     "peak": PEAK["f32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
+                     "traffic": None},
+        "cpu_baseline": None,
     }
     print(json.dumps(out))
 

@@ -21,6 +21,16 @@ struct LayerShape {
     int win, wout, nb;
 };
 
+// Many independent instances on one concatenated point axis (batched plans).
+// Each instance's points start at a multiple of 256, so every 128-point
+// group, 256-point block and tile belongs to one instance. Null tile_inst:
+// a single instance.
+struct BatchMap {
+    const int *tile_inst = nullptr;   // instance of each 128-point group
+    int64_t w_stride = 0;             // elements between consecutive instances' weights
+    const int4 *slices = nullptr;     // weight-gradient slices {instance, p_begin, p_end, -}
+};
+
 // ---- generic kernels (any supported dtype as T = float / double) ----------
 template <typename T>
 hipError_t launch_fwd_generic(ChanCfg ch, bool first, const T *zin, const T *W, T *zout,

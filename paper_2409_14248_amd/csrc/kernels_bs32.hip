@@ -262,7 +262,7 @@ template <int O0, int O1, bool FIRST, int NQ, int S>
 __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const float *__restrict__ zin,
                                                    const float *__restrict__ W,
                                                    float *__restrict__ zout, int64_t n, int win,
-                                                   int KI, GridP<float> g)
+                                                   int KI, GridP<float> g, BatchMap bm)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int RG = (C + 3) / 4;
@@ -289,16 +289,20 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
     const int64_t ntiles = (n + TPK - 1) / TPK;
     const int njc = (win + KJ - 1) / KJ;
     const bool single = KI >= win;
+    // batched: the weights of the tile's instance, restaged when it changes
+    const bool batched = bm.tile_inst != nullptr;
+    const float *Wc = W;
+    int cur_inst = -1;
     auto stage = [&](int i0, int nin) {
         if constexpr (S == 0) {
-            stage_rows<NT8>(sW, W, i0 * nb, nin * nb, N, NS);
+            stage_rows<NT8>(sW, Wc, i0 * nb, nin * nb, N, NS);
         } else {
-            stage_pairs<NT8, false>(sP, W, i0, nin, nb, N, NS);
-            if constexpr (S == 3) stage_pairs<NT8, true>(sPl, W, i0, nin, nb, N, NS);
+            stage_pairs<NT8, false>(sP, Wc, i0, nin, nb, N, NS);
+            if constexpr (S == 3) stage_pairs<NT8, true>(sPl, Wc, i0, nin, nb, N, NS);
         }
     };
     JCk::zero_rows(sZ);
-    if (single) stage(0, win);
+    if (single && !batched) stage(0, win);
 
     // this lane's channel rows: coefficient sources (offsets in a staged input)
     float a0[RG];
@@ -325,9 +329,16 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
         }
         const int ib = jc * KJ;
         const int iW = single ? 0 : (ib / KI) * KI;
+        bool restage = false;
+        if (batched && jc == 0) {
+            const int inst = bm.tile_inst[(tile * TPK) >> 7];
+            restage = inst != cur_inst;
+            cur_inst = inst;
+            Wc = W + (int64_t)inst * bm.w_stride;
+        }
         __syncthreads();
         pre.store(sZ);
-        if (!single && ib % KI == 0) stage(iW, min(KI, win - iW));
+        if ((!single && ib % KI == 0) || restage) stage(iW, min(KI, win - iW));
         __syncthreads();
         const int64_t cur_tile = tile;
         if (++jc == njc) {
@@ -442,7 +453,7 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
                                                   const float *__restrict__ ybar,
                                                   const float *__restrict__ W,
                                                   float *__restrict__ zbar, int64_t n, int win,
-                                                  int KI, GridP<float> g)
+                                                  int KI, GridP<float> g, BatchMap bm)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int RG = (C + 3) / 4;
@@ -471,15 +482,18 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
     const int64_t ntiles = (n + TPK - 1) / TPK;
     const int njc = (win + KJ - 1) / KJ;
     const bool single = KI >= win;
+    const bool batched = bm.tile_inst != nullptr;
+    const float *Wc = W;
+    int cur_inst = -1;
     auto stage = [&](int i0, int nin) {
         if constexpr (S == 0) {
-            stage_rows<NT8>(sW, W, i0 * nb, nin * nb, N, NS);
+            stage_rows<NT8>(sW, Wc, i0 * nb, nin * nb, N, NS);
         } else {
-            stage_rows_bf16<NT8, false>(sH, W, i0 * nb, nin * nb, N, NSH);
-            if constexpr (S == 3) stage_rows_bf16<NT8, true>(sHl, W, i0 * nb, nin * nb, N, NSH);
+            stage_rows_bf16<NT8, false>(sH, Wc, i0 * nb, nin * nb, N, NSH);
+            if constexpr (S == 3) stage_rows_bf16<NT8, true>(sHl, Wc, i0 * nb, nin * nb, N, NSH);
         }
     };
-    if (single) stage(0, win);
+    if (single && !batched) stage(0, win);
 
     JCk pre;
     int64_t tile = blockIdx.x;
@@ -519,9 +533,16 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
         }
         const int ib = jc * KJ;
         const int iW = single ? 0 : (ib / KI) * KI;
+        bool restage = false;
+        if (batched && jc == 0) {
+            const int inst = bm.tile_inst[(cur_tile * TPK) >> 7];
+            restage = inst != cur_inst;
+            cur_inst = inst;
+            Wc = W + (int64_t)inst * bm.w_stride;
+        }
         __syncthreads();
         pre.store(sZ);
-        if (!single && ib % KI == 0) stage(iW, min(KI, win - iW));
+        if ((!single && ib % KI == 0) || restage) stage(iW, min(KI, win - iW));
         __syncthreads();
         if (++jc == njc) {
             jc = 0;
@@ -640,7 +661,7 @@ template <int O0, int O1, bool FIRST, int NQ, int II, int S>
 __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
                                               const float *__restrict__ ybar,
                                               float *__restrict__ part, int64_t n, int win,
-                                              int nsplit, int WI, GridP<float> g)
+                                              int nsplit, int WI, GridP<float> g, BatchMap bm)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int CP = C <= 4 ? 4 : 8;       // padded channel stride in LDS
@@ -674,7 +695,12 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
     const int i0 = blockIdx.x * IBe;
     const int split = blockIdx.y;
     const int64_t per = ((n + nsplit - 1) / nsplit + PC - 1) / PC * PC;
-    const int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
+    int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
+    if (bm.slices) {
+        const int4 sl = bm.slices[split];
+        ps = sl.y;
+        pe = sl.z;
+    }
     for (int e = threadIdx.x; e < IB * IS; e += NT) sG[e] = 0.f;
     float *gbase = sG + (wp * IBe + ii) * IS + 4 * jc + s;
 
@@ -847,13 +873,15 @@ template <int O0, int O1>
 __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
                                                  const float *__restrict__ W,
                                                  float *__restrict__ out, int64_t n, int win,
-                                                 GridP<float> g)
+                                                 GridP<float> g, BatchMap bm)
 {
     constexpr int C = Ch<O0, O1>::C;
     extern __shared__ float sW[];
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
-    for (int e = threadIdx.x; e < win * nb; e += NT) sW[e] = W[e];
+    const float *Wb = W;
+    if (bm.tile_inst) Wb += (int64_t)bm.tile_inst[((int64_t)blockIdx.x * NT) >> 7] * bm.w_stride;
+    for (int e = threadIdx.x; e < win * nb; e += NT) sW[e] = Wb[e];
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (p >= n) return;
@@ -895,13 +923,14 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
                                                 const float *__restrict__ ybar,
                                                 const float *__restrict__ W,
                                                 float *__restrict__ zbar, int64_t n, int win,
-                                                GridP<float> g)
+                                                GridP<float> g, BatchMap bm)
 {
     constexpr int C = Ch<O0, O1>::C;
     const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (e >= n * win) return;
     const int i = (int)(e / n);
     const int64_t p = e % n;
+    if (bm.tile_inst) W += (int64_t)bm.tile_inst[p >> 7] * bm.w_stride;
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     float zj[C], yb[C], zb[C];
@@ -933,7 +962,7 @@ template <int O0, int O1>
 __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
                                                 const float *__restrict__ ybar,
                                                 float *__restrict__ part, int64_t n, int win,
-                                                int nsplit, GridP<float> g)
+                                                int nsplit, GridP<float> g, BatchMap bm)
 {
     constexpr int C = Ch<O0, O1>::C;
     constexpr int IB = NT / DL_SL;        // inputs per block
@@ -944,7 +973,12 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
     const int i = blockIdx.x * IB + li;
     const int split = blockIdx.y;
     const int64_t per = (n + nsplit - 1) / nsplit;
-    const int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
+    int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
+    if (bm.slices) {
+        const int4 sl = bm.slices[split];
+        ps = sl.y;
+        pe = sl.z;
+    }
     for (int b = 0; b < nb; ++b) sacc[threadIdx.x][b] = 0.f;
     if (i < win) {
         constexpr int U = 4;                    // points whose loads are in flight together
@@ -1117,13 +1151,13 @@ static void w_stage(LayerShape ls, int C, int S, bool fwd, int &KI, size_t &byte
 
 hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float *W, float *zout,
                            int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, int S,
-                           hipStream_t st)
+                           hipStream_t st, const BatchMap &bm)
 {
     if (n <= 0) return hipSuccess;
     if (ls.wout == 1) {
         const size_t sh = sizeof(float) * ls.win * ls.nb;
         HRK_CH_SWITCH32(ch, {
-            k_fwd_last<O0, O1><<<(unsigned)((n + NT - 1) / NT), NT, sh, st>>>(zin, W, zout, n, ls.win, g);
+            k_fwd_last<O0, O1><<<(unsigned)((n + NT - 1) / NT), NT, sh, st>>>(zin, W, zout, n, ls.win, g, bm);
         });
         return hipGetLastError();
     }
@@ -1137,11 +1171,11 @@ hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float
             if (first) {
                 auto kf = k_fwd_bs<O0, O1, true, NQ, S>;
                 set_lds_limit((const void *)kf);
-                kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
+                kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g, bm);
             } else {
                 auto kf = k_fwd_bs<O0, O1, false, NQ, S>;
                 set_lds_limit((const void *)kf);
-                kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g);
+                kf<<<grid, NT8, sh, st>>>(zin, W, zout, n, ls.win, KI, g, bm);
             }
         });
     });
@@ -1150,13 +1184,13 @@ hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float
 
 hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const float *W, float *zbar,
                           int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, int S,
-                          hipStream_t st)
+                          hipStream_t st, const BatchMap &bm)
 {
     if (n <= 0) return hipSuccess;
     if (ls.wout == 1) {
         HRK_CH_SWITCH32(ch, {
             k_dx_last<O0, O1><<<(unsigned)((n * ls.win + NT - 1) / NT), NT, 0, st>>>(zin, ybar, W, zbar, n,
-                                                                                   ls.win, g);
+                                                                                   ls.win, g, bm);
         });
         return hipGetLastError();
     }
@@ -1169,7 +1203,7 @@ hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const
         HRK_NQ_SWITCH(ls.wout, {
             auto kf = k_dx_bs<O0, O1, NQ, S>;
             set_lds_limit((const void *)kf);
-            kf<<<grid, NT8, sh, st>>>(zin, ybar, W, zbar, n, ls.win, KI, g);
+            kf<<<grid, NT8, sh, st>>>(zin, ybar, W, zbar, n, ls.win, KI, g, bm);
         });
     });
     return hipGetLastError();
@@ -1181,10 +1215,12 @@ hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const
 struct DwTile {
     int II, WI;
 };
-static DwTile dw_tile(LayerShape ls, int C)
+static DwTile dw_tile(LayerShape ls, int C, int ii_override = 0)
 {
     int ii = dw_ii(ls, C);
     if (ii == 0) return {0, 0};
+    if (ii_override && 16 / ii_override <= ls.wout / 4 && dw_bs_lds(C, ls.nb, ls.wout, ii_override) <= LDS_MAX)
+        ii = ii_override;
     while (ii > 2 && ii / 2 >= ls.win && 16 / (ii / 2) <= ls.wout / 4) ii /= 2;
     const int groups = (ls.win + ii - 1) / ii;
     const int wi = groups >= 4 ? 4 : groups >= 2 ? 2 : 1;
@@ -1209,16 +1245,17 @@ int dw_bs32_splits(int64_t n, LayerShape ls)
 }
 
 hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float *ybar, float *part,
-                          int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, int S, hipStream_t st)
+                          int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, int S, hipStream_t st,
+                          const BatchMap &bm, int dw_ii_override)
 {
     if (ls.wout == 1) {
         dim3 grid((unsigned)((ls.win + NT / DL_SL - 1) / (NT / DL_SL)), (unsigned)nsplit);
         HRK_CH_SWITCH32(ch, {
-            k_dw_last<O0, O1><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, nsplit, g);
+            k_dw_last<O0, O1><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, nsplit, g, bm);
         });
         return hipGetLastError();
     }
-    const DwTile tl = dw_tile(ls, ch.C());
+    const DwTile tl = dw_tile(ls, ch.C(), dw_ii_override);
     if (tl.II == 0) return hipErrorInvalidValue;
     const int ibe = tl.II * tl.WI;
     const dim3 grid((unsigned)((ls.win + ibe - 1) / ibe), (unsigned)nsplit);
@@ -1231,11 +1268,11 @@ hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float 
                     if (first) {
                         auto kf = k_dw_bs<O0, O1, true, NQ, II, S>;
                         set_lds_limit((const void *)kf);
-                        kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g);
+                        kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g, bm);
                     } else {
                         auto kf = k_dw_bs<O0, O1, false, NQ, II, S>;
                         set_lds_limit((const void *)kf);
-                        kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g);
+                        kf<<<grid, NT, sh, st>>>(zin, ybar, part, n, ls.win, nsplit, wi, g, bm);
                     }
                 }
             });

@@ -261,6 +261,18 @@ WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
     return L;
 }
 
+int check_pde(const hrkan_pde_desc *pde)
+{
+    if (!pde) return fail(HRKAN_ERR_INVALID_ARG, "pde is NULL");
+    if (pde->kind != HRKAN_POISSON2D && pde->kind != HRKAN_BURGERS1D)
+        return fail(HRKAN_ERR_INVALID_ARG, "pde kind %d unknown", pde->kind);
+    if (!std::isfinite(pde->nu) || !std::isfinite(pde->alpha) || !std::isfinite(pde->adv))
+        return fail(HRKAN_ERR_INVALID_ARG, "pde coefficients must be finite");
+    return HRKAN_OK;
+}
+
+uint32_t pde_mask(int kind) { return kind == HRKAN_POISSON2D ? HRKAN_MASK_POISSON : HRKAN_MASK_BURGERS; }
+
 }  // namespace hrk
 
 using namespace hrk;
@@ -442,17 +454,6 @@ int check_weights(const NetInfo &ni, const void *const *W, const char *what)
     return HRKAN_OK;
 }
 
-int check_pde(const hrkan_pde_desc *pde)
-{
-    if (!pde) return fail(HRKAN_ERR_INVALID_ARG, "pde is NULL");
-    if (pde->kind != HRKAN_POISSON2D && pde->kind != HRKAN_BURGERS1D)
-        return fail(HRKAN_ERR_INVALID_ARG, "pde kind %d unknown", pde->kind);
-    if (!std::isfinite(pde->nu) || !std::isfinite(pde->alpha) || !std::isfinite(pde->adv))
-        return fail(HRKAN_ERR_INVALID_ARG, "pde coefficients must be finite");
-    return HRKAN_OK;
-}
-
-uint32_t pde_mask(int kind) { return kind == HRKAN_POISSON2D ? HRKAN_MASK_POISSON : HRKAN_MASK_BURGERS; }
 
 }  // namespace
 

@@ -35,6 +35,8 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int check_net(const hrkan_net_desc *d, NetInfo *ni);
 int mask_cfg(uint32_t mask, ChanCfg *ch);
+int check_pde(const hrkan_pde_desc *pde);
+uint32_t pde_mask(int kind);   // the interior channel mask of a PDE kind
 template <typename T> GridP<T> make_grid(const NetInfo &ni);
 int64_t saved_elems(const NetInfo &ni, int C, int64_t n);
 int dw_splits(const NetInfo &ni, int l, int64_t n);

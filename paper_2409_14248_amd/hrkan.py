@@ -391,3 +391,83 @@ class HRKANResidual(torch.autograd.Function):
         seed_int, seed_bc = ctx.saved_tensors
         g = gL.to(seed_int.dtype)
         return None, None, seed_int * g, seed_bc * g, None, None
+
+
+# ---------------------------------------------------------------------------
+# batched plans: many independent instances of one network, one graph launch
+# ---------------------------------------------------------------------------
+def _points_array(xs_int, xs_bc, gs_bc):
+    arr = (Points * len(xs_int))()
+    for q, (xi, xb, g) in enumerate(zip(xs_int, xs_bc, gs_bc)):
+        arr[q] = Points(xi.data_ptr() if xi.numel() else None, xi.shape[0],
+                        xb.data_ptr() if xb.numel() else None, xb.shape[0],
+                        g.data_ptr() if g.numel() else None)
+    return arr
+
+
+def plan_workspace_bytes(nd: NetDesc, n_int: Sequence[int], n_bc: Sequence[int]) -> int:
+    arr = (Points * len(n_int))()
+    for q, (a, b) in enumerate(zip(n_int, n_bc)):
+        arr[q] = Points(None, int(a), None, int(b), None)
+    b = ctypes.c_size_t(0)
+    check(lib().hrkan_plan_workspace_bytes(ctypes.byref(nd), len(n_int), arr, ctypes.byref(b)))
+    return b.value
+
+
+class Plan:
+    """A batched step over instances of one network shape (hrkan_plan_*).
+
+    Holds device copies of every instance's points, the packed weights
+    W_packed [n_inst, n_params] (updated in place by the caller between
+    steps), and the outputs loss [n_inst, 3] (float64) and gW [n_inst,
+    n_params]. execute() is one HIP graph launch."""
+
+    def __init__(self, problems: Sequence[_wl.Problem], device="cuda", stream=None):
+        net = problems[0].net
+        self.nd = net_desc(net, "f32")
+        self.n_inst = len(problems)
+        to = lambda a, shape=None: torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
+        self.x_int = [to(p.x_int) for p in problems]
+        self.x_bc = [to(p.x_bc) for p in problems]
+        self.g_bc = [to(p.g_bc) for p in problems]
+        self.W = torch.stack([torch.cat([to(w).reshape(-1) for w in p.W]) for p in problems]).contiguous()
+        self.gW = torch.empty_like(self.W)
+        self.loss = torch.empty(self.n_inst, 3, dtype=torch.float64, device=device)
+        self.pts = _points_array(self.x_int, self.x_bc, self.g_bc)
+        pdes = (PdeDesc * self.n_inst)(*[pde_desc(p.pde) for p in problems])
+        nbytes = ctypes.c_size_t(0)
+        check(lib().hrkan_plan_workspace_bytes(ctypes.byref(self.nd), self.n_inst, self.pts,
+                                               ctypes.byref(nbytes)))
+        self.ws = alloc_workspace(nbytes.value, device)
+        h = ctypes.c_void_p(None)
+        check(lib().hrkan_plan_create(ctypes.byref(h), ctypes.byref(self.nd), self.n_inst, pdes,
+                                      _ptr(self.W), self.pts, _ptr(self.loss), _ptr(self.gW), _ptr(self.ws),
+                                      self.ws.numel(), _stream(stream)))
+        self._h = h
+
+    def execute(self, stream=None) -> None:
+        check(lib().hrkan_plan_execute(self._h, _stream(stream)))
+
+    def config(self):
+        tp, bl = ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib().hrkan_plan_config(self._h, ctypes.byref(tp), ctypes.byref(bl)))
+        return tp.value, bl.value
+
+    def layer_grads(self, q: int, net: _wl.Net) -> List[torch.Tensor]:
+        """Instance q's gradient, split into the per-layer [w_l * n_b, w_{l+1}] arrays."""
+        out, o = [], 0
+        for r, c in net.weight_shapes():
+            out.append(self.gW[q, o:o + r * c].reshape(r, c))
+            o += r * c
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().hrkan_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

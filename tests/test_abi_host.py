@@ -210,3 +210,27 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(H, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         H.lib()
+
+
+def test_plan_workspace_validation():
+    nd = nd_of((2, 32, 32, 1), G=10)
+    assert H.plan_workspace_bytes(nd, [5000, 300], [300, 20]) > 0
+    # workspace grows with the points
+    assert H.plan_workspace_bytes(nd, [50000, 300], [3000, 20]) > H.plan_workspace_bytes(nd, [5000, 300], [300, 20])
+    with pytest.raises(H.HrkanError) as e:
+        H.plan_workspace_bytes(nd, [], [])
+    assert e.value.code == H.ERR_INVALID_ARG
+    with pytest.raises(H.HrkanError) as e:
+        H.plan_workspace_bytes(nd, [-1], [4])
+    assert e.value.code == H.ERR_INVALID_ARG
+    for bad in (nd_of((2, 32, 32, 1), G=10, dtype="f64"), nd_of((2, 8, 1), G=5)):
+        with pytest.raises(H.HrkanError) as e:
+            H.plan_workspace_bytes(bad, [100], [10])
+        assert e.value.code == H.ERR_UNSUPPORTED
+
+
+def test_plan_calls_reject_null_plan():
+    L = H.lib()
+    assert L.hrkan_plan_execute(None, None) == H.ERR_PLAN_MISMATCH
+    assert L.hrkan_plan_config(None, None, None) == H.ERR_PLAN_MISMATCH
+    L.hrkan_plan_destroy(None)

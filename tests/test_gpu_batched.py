@@ -1,0 +1,87 @@
+"""The batched step (hrkan_plan_*): many Burgers instances of one network
+shape, each with its own weights, viscosity and point counts, run as one
+HIP graph launch over a concatenated point axis.
+
+Each instance's loss and gradient must equal what the single-instance step
+(hrkan_step) gives for that instance alone, within FP32 summation-order
+differences (the two paths slice the weight-gradient sums differently), and
+one instance is checked against the FP64 oracle at the FP32 gate.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from conftest import relerr
+from gpu_util import gpu_step
+from paper_2409_14248_amd import hrkan as H
+from paper_2409_14248_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+SAME_STEP_TOL = 2e-5
+
+
+def _instances(n, lo=200, hi=5000):
+    return WL.batched_instances(WL.WORKLOADS["burgers_batched_c5"], n_instances=n, lo=lo, hi=hi)
+
+
+def _check_against_single_steps(plan, probs):
+    torch.cuda.synchronize()
+    loss = plan.loss.cpu().numpy()
+    for q, pr in enumerate(probs):
+        ls, gW, _ = gpu_step(pr, "f32")
+        assert relerr(loss[q], ls) <= SAME_STEP_TOL, (q, loss[q], ls)
+        for l, g in enumerate(plan.layer_grads(q, pr.net)):
+            assert relerr(g.double().cpu().numpy(), gW[l]) <= SAME_STEP_TOL, (q, l)
+
+
+def test_batched_step_matches_single_instance_steps():
+    probs = _instances(7)
+    # an instance whose counts are not multiples of anything, and a tiny one
+    probs[2] = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=1001, n_bc=4, seed=77,
+                               pde=WL.Pde(WL.BURGERS1D, 0.004))
+    probs[5] = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=3, n_bc=4, seed=78,
+                               pde=WL.Pde(WL.BURGERS1D, 0.05))
+    plan = H.Plan(probs)
+    plan.execute()
+    _check_against_single_steps(plan, probs)
+    tp, blocks = plan.config()
+    assert tp in (1024, 2048, 4096) and blocks > 0
+    assert H.read_status(plan.ws) == 0
+
+
+def test_batched_instance_matches_oracle():
+    probs = _instances(3, lo=2000, hi=3000)
+    plan = H.Plan(probs)
+    plan.execute()
+    torch.cuda.synchronize()
+    q = probs[1].rounded(np.float32)
+    ref = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
+    assert relerr(plan.loss[1].cpu().numpy(), ref["loss"]) < 1e-5
+    for l, g in enumerate(plan.layer_grads(1, q.net)):
+        assert relerr(g.double().cpu().numpy(), ref["gW"][l]) < 1e-5, l
+
+
+def test_batched_replays_are_identical_and_follow_weight_updates():
+    probs = _instances(5)
+    plan = H.Plan(probs)
+    plan.execute()
+    torch.cuda.synchronize()
+    l1, g1 = plan.loss.clone(), plan.gW.clone()
+    plan.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(l1, plan.loss) and torch.equal(g1, plan.gW)
+    # a step of plain gradient descent on every instance, then the next step
+    with torch.no_grad():
+        plan.W -= 1e-3 * plan.gW
+    plan.execute()
+    torch.cuda.synchronize()
+    new = []
+    for q, pr in enumerate(probs):
+        Ws, o = [], 0
+        for r, c in pr.net.weight_shapes():
+            Ws.append(plan.W[q, o:o + r * c].reshape(r, c).double().cpu().numpy())
+            o += r * c
+        new.append(WL.Problem(pr.net, pr.pde, Ws, pr.x_int, pr.x_bc, pr.g_bc))
+    _check_against_single_steps(plan, new)
