@@ -8,7 +8,8 @@ namespace hrk {
 // Matrix-core kernels for k = 3, m = 4: block-sparse MFMA for the forward,
 // input-bar and weight-gradient contractions (one collocation point per
 // 4x4 block), vector-ALU kernels for a one-output layer.
-bool bs32_supported(LayerShape ls);
+// Layer shapes the matrix-core kernels take (first: the network's input layer).
+bool bs32_supported(LayerShape ls, bool first);
 // S = 0: FP32 products; S = 1..3: BF16 products with S terms (hrkan.h,
 // bf16_split), FP32 accumulation. BF16 covers the Poisson, Burgers and
 // boundary-value channel sets.

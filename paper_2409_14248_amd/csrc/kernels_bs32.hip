@@ -33,8 +33,16 @@ constexpr int NT = 256;                 // threads of the 4-wave kernels
 constexpr int NT8 = 512;                // threads of the 8-wave kernels
 constexpr int PW = 16;                  // points per wave
 constexpr int TP = 8 * PW;              // points per tile of an 8-wave block
-constexpr int KJ = 4;                   // inputs per staged jet chunk
-constexpr int LDS_FWD = 78 * 1024;      // per 8-wave block: two blocks per CU
+// inputs per staged jet chunk: both inputs of a first layer, else 8 (4 for
+// 5-channel sets, whose chunks are larger); hidden widths are multiples of 8
+constexpr int kj_of(bool first, int C) { return first ? 2 : (C <= 4 ? 8 : 4); }
+constexpr int LDS_FWD = 80 * 1024;      // per 8-wave block: two blocks per CU
+
+// Output groups of the 8-wave kernels: the waves of a block split the outputs
+// into OG groups (tiles of 128/OG points), so that a lane holds at most 8
+// output quads; single-channel sets (boundary values) always split in 4, which
+// gives their small point counts 4 times as many tiles.
+constexpr int og_of(int C, int NQ) { return C == 1 ? 4 : NQ / 8; }
 
 // Waves per SIMD the 8-wave kernels are compiled for: two blocks per CU
 // (registers <= 128) when a point's channels fit one 4-row group.
@@ -201,7 +209,7 @@ __device__ __forceinline__ void stage_rows_bf16(unsigned short *sH, const float 
 // A chunk of KJ inputs' jets for a tile of TPC points, prefetched into
 // registers one chunk ahead and stored to LDS as [input][channel][point] with
 // C + 1 channel rows per input (the last one stays zero).
-template <int O0, int O1, bool FIRST, int BLK, int TPC>
+template <int O0, int O1, bool FIRST, int BLK, int TPC, int KJ>
 struct JetChunk {
     static constexpr int C = Ch<O0, O1>::C;
     static constexpr int CS = (C + 1) * TPC;     // floats per staged input
@@ -268,10 +276,12 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
     constexpr int RG = (C + 3) / 4;
     constexpr int N = 4 * NQ;
     constexpr int NS = N + 4;
-    constexpr int OG = NQ / 8;               // output groups: the waves split the outputs
+    constexpr int OG = og_of(C, NQ);         // output groups: the waves split the outputs
     constexpr int NQW = NQ / OG;             // output quads per lane
+    constexpr int VW = NQW >= 4 ? 4 : 2;     // outputs per LDS weight read
     constexpr int TPK = TP / OG;             // points per tile
-    using JCk = JetChunk<O0, O1, FIRST, NT8, TPK>;
+    constexpr int KJ = kj_of(FIRST, C);
+    using JCk = JetChunk<O0, O1, FIRST, NT8, TPK, KJ>;
     constexpr int CS = JCk::CS;
     extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
     const int og = wv % OG, pt = (wv / OG) * PW + bl;
     const int col0 = og * 4 * NQW + s * NQW;   // this lane's first output
     const int64_t ntiles = (n + TPK - 1) / TPK;
-    const int njc = (win + KJ - 1) / KJ;
+    const int njc = win / KJ;                // win is a multiple of KJ
     const bool single = KI >= win;
     // batched: the weights of the tile's instance, restaged when it changes
     const bool batched = bm.tile_inst != nullptr;
@@ -302,7 +312,6 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
         }
     };
     JCk::zero_rows(sZ);
-    if (single && !batched) stage(0, win);
 
     // this lane's channel rows: coefficient sources (offsets in a staged input)
     float a0[RG];
@@ -318,7 +327,8 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
     JCk pre;
     int64_t tile = blockIdx.x;
     int jc = 0;
-    if (tile < ntiles) pre.load(zin, n, win, tile, 0);
+    if (tile < ntiles) pre.load(zin, n, win, tile, 0);   // in flight while the weights are staged
+    if (single && !batched) stage(0, win);
     f4 acc[RG][NQW];
     while (tile < ntiles) {
         if (jc == 0) {
@@ -347,9 +357,10 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
         }
         if (tile < ntiles) pre.load(zin, n, win, tile, jc);
 
-        const int ie = min(win, ib + KJ);
-        for (int i = ib; i < ie; ++i) {
-            const float *zc = sZ + (i - ib) * CS;
+#pragma unroll
+        for (int il = 0; il < KJ; ++il) {
+            const int i = ib + il;
+            const float *zc = sZ + il * CS;
             const float zt = zc[pt] * inv_w + zoff;
             const int qa = window_k3(zt, nb);
             float v[3];
@@ -372,12 +383,18 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
                 for (int t = 0; t < 4; ++t) {
                     float bw[NQW];
 #pragma unroll
-                    for (int k4 = 0; k4 < NQW / 4; ++k4) {
-                        const f4 w4 = *reinterpret_cast<const f4 *>(wr + t * NS + 4 * k4);
-                        bw[4 * k4 + 0] = w4[0];
-                        bw[4 * k4 + 1] = w4[1];
-                        bw[4 * k4 + 2] = w4[2];
-                        bw[4 * k4 + 3] = w4[3];
+                    for (int k = 0; k < NQW; k += VW) {
+                        if constexpr (VW == 4) {
+                            const f4 w4 = *reinterpret_cast<const f4 *>(wr + t * NS + k);
+                            bw[k + 0] = w4[0];
+                            bw[k + 1] = w4[1];
+                            bw[k + 2] = w4[2];
+                            bw[k + 3] = w4[3];
+                        } else {
+                            const f2 w2 = *reinterpret_cast<const f2 *>(wr + t * NS + k);
+                            bw[k + 0] = w2[0];
+                            bw[k + 1] = w2[1];
+                        }
                     }
 #pragma unroll
                     for (int r = 0; r < RG; ++r) {
@@ -402,17 +419,26 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
                 }
                 const int prow = ((i - iW) * (nb - 1) + qa) * NS + col0;
 #pragma unroll
-                for (int k4 = 0; k4 < NQW / 4; ++k4) {
-                    const u4 p01 = *reinterpret_cast<const u4 *>(sP + prow + 4 * k4);
-                    const u4 p23 = *reinterpret_cast<const u4 *>(sP + prow + 2 * NS + 4 * k4);
-                    u4 q01, q23;
+                for (int k0 = 0; k0 < NQW; k0 += VW) {
+                    unsigned int p01[VW], p23[VW], q01[VW], q23[VW];
+                    auto ld = [&](const unsigned int *src, unsigned int *dst) {
+                        if constexpr (VW == 4) {
+                            const u4 v = *reinterpret_cast<const u4 *>(src);
+                            dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2]; dst[3] = v[3];
+                        } else {
+                            const u2 v = *reinterpret_cast<const u2 *>(src);
+                            dst[0] = v[0]; dst[1] = v[1];
+                        }
+                    };
+                    ld(sP + prow + k0, p01);
+                    ld(sP + prow + 2 * NS + k0, p23);
                     if constexpr (S == 3) {
-                        q01 = *reinterpret_cast<const u4 *>(sPl + prow + 4 * k4);
-                        q23 = *reinterpret_cast<const u4 *>(sPl + prow + 2 * NS + 4 * k4);
+                        ld(sPl + prow + k0, q01);
+                        ld(sPl + prow + 2 * NS + k0, q23);
                     }
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int k = 4 * k4 + e;
+                    for (int e = 0; e < VW; ++e) {
+                        const int k = k0 + e;
                         const s4 bh = mk4(p01[e], p23[e]);
 #pragma unroll
                         for (int r = 0; r < RG; ++r) {
@@ -461,10 +487,11 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
     constexpr int NS = N + 4;                // FP32 row stride (floats)
     constexpr int NSH = N + 8;               // BF16 row stride (halfwords)
     constexpr int SA = S >= 2 ? 2 : 1;       // pieces of the bar operand
-    constexpr int OG = NQ / 8;               // output groups: the waves split the outputs
+    constexpr int OG = og_of(C, NQ);         // output groups: the waves split the outputs
     constexpr int NQW = NQ / OG;             // output quads per wave
     constexpr int TPK = TP / OG;             // points per tile
-    using JCk = JetChunk<O0, O1, false, NT8, TPK>;
+    constexpr int KJ = kj_of(false, C);
+    using JCk = JetChunk<O0, O1, false, NT8, TPK, KJ>;
     constexpr int CS = JCk::CS;
     extern __shared__ __align__(16) float smem[];
     const int nb = g.nb;
@@ -480,7 +507,7 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
     const int og = wv % OG, pt = (wv / OG) * PW + bl;
     const int jb = og * 4 * NQW;             // this wave's first output
     const int64_t ntiles = (n + TPK - 1) / TPK;
-    const int njc = (win + KJ - 1) / KJ;
+    const int njc = win / KJ;                // win is a multiple of KJ
     const bool single = KI >= win;
     const bool batched = bm.tile_inst != nullptr;
     const float *Wc = W;
@@ -493,12 +520,11 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
             if constexpr (S == 3) stage_rows_bf16<NT8, true>(sHl, Wc, i0 * nb, nin * nb, N, NSH);
         }
     };
-    if (single && !batched) stage(0, win);
-
     JCk pre;
     int64_t tile = blockIdx.x;
     int jc = 0;
-    if (tile < ntiles) pre.load(zin, n, win, tile, 0);
+    if (tile < ntiles) pre.load(zin, n, win, tile, 0);   // in flight while the weights are staged
+    if (single && !batched) stage(0, win);
     // the output bars of this lane's channel rows: FP32 (S = 0) or BF16 pieces
     float yb[S == 0 ? RG : 1][S == 0 ? 4 * NQW : 1];
     s4 ybp[S == 0 ? 1 : RG][S == 0 ? 1 : NQW][SA];
@@ -550,9 +576,10 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
         }
         if (tile < ntiles) pre.load(zin, n, win, tile, jc);
 
-        const int ie = min(win, ib + KJ);
-        for (int i = ib; i < ie; ++i) {
-            const float *zc = sZ + (i - ib) * CS + pt;
+#pragma unroll
+        for (int il = 0; il < KJ; ++il) {
+            const int i = ib + il;
+            const float *zc = sZ + il * CS + pt;
             float zj[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) zj[c] = zc[c * TPK];
@@ -620,13 +647,12 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
                 // this wave's part of the sum over outputs; the groups are
                 // added in order once the chunk is done
 #pragma unroll
-                for (int c = 0; c < C; ++c) sRed[((og * KJ + (i - ib)) * C + c) * TPK + pt] = zb[c];
+                for (int c = 0; c < C; ++c) sRed[((og * KJ + il) * C + c) * TPK + pt] = zb[c];
             }
         }
         if constexpr (OG > 1) {
             __syncthreads();
-            const int nin = ie - ib;
-            for (int e = threadIdx.x; e < nin * C * TPK; e += NT8) {
+            for (int e = threadIdx.x; e < KJ * C * TPK; e += NT8) {
                 const int pp = e % TPK, c = (e / TPK) % C, il = e / (TPK * C);
                 const int64_t pq = cur_tile * TPK + pp;
                 float v = sRed[((0 * KJ + il) * C + c) * TPK + pp];
@@ -655,7 +681,10 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
 // N outputs of one slice; the next chunk of points is loaded while the
 // current one is computed.
 // ---------------------------------------------------------------------------
-template <int NQ> constexpr int dw_pc() { return NQ >= 32 ? 8 : 16; }
+// points per staged chunk: wide layers 8 (LDS), 2-input-per-wave tiles of
+// 32-output layers 64 (short per-point work: fewer, larger chunks keep the
+// global loads ahead of the compute), else 16
+template <int NQ, int II> constexpr int dw_pc() { return NQ >= 32 ? 8 : (II == 2 && NQ <= 8) ? 64 : 16; }
 
 template <int O0, int O1, bool FIRST, int NQ, int II, int S>
 __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
@@ -673,7 +702,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
     constexpr int IB = 4 * II;               // staged inputs (WI * II of them real)
     constexpr int JC = 16 / II;              // 4-output chunks per MFMA
     constexpr int PASSES = NQ / JC;
-    constexpr int PC = dw_pc<NQ>();
+    constexpr int PC = dw_pc<NQ, II>();
     constexpr int JS = IB * CP + 4;          // staged jets: stride per point
     constexpr int YS = N * CP + 4;           // staged bars: stride per point
     constexpr int EJ = C * IB * PC, EY = C * N * PC;
@@ -860,7 +889,8 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
 
 static size_t dw_bs_lds(int C, int nb, int N, int II)
 {
-    const int CP = C <= 4 ? 4 : 8, IB = 4 * II, PC = N >= 128 ? 8 : 16, JC = 16 / II;
+    const int CP = C <= 4 ? 4 : 8, IB = 4 * II, JC = 16 / II;
+    const int PC = N >= 128 ? 8 : (II == 2 && N <= 32) ? 64 : 16;
     return sizeof(float) *
            ((size_t)IB * (nb * N + 4 * JC) + (size_t)PC * (IB * CP + 4) + (size_t)PC * (N * CP + 4));
 }
@@ -868,7 +898,10 @@ static size_t dw_bs_lds(int C, int nb, int N, int II)
 // ---------------------------------------------------------------------------
 // last layer (one output): plain vector-ALU kernels
 // ---------------------------------------------------------------------------
-// u_c[p] = sum_i sum_t W[i*nb + qa + t] * A_c(p, i, t); one thread per point
+// u_c[p] = sum_i sum_t W[i*nb + qa + t] * A_c(p, i, t); 4 threads per point
+// (consecutive lanes), each taking every 4th input with all its loads in
+// flight, the 4 partial sums added across the quad.
+constexpr int FL_U = 8;   // inputs per thread whose loads are in flight together
 template <int O0, int O1>
 __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
                                                  const float *__restrict__ W,
@@ -880,25 +913,27 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     const float *Wb = W;
-    if (bm.tile_inst) Wb += (int64_t)bm.tile_inst[((int64_t)blockIdx.x * NT) >> 7] * bm.w_stride;
+    if (bm.tile_inst) Wb += (int64_t)bm.tile_inst[((int64_t)blockIdx.x * (NT / 4)) >> 7] * bm.w_stride;
     for (int e = threadIdx.x; e < win * nb; e += NT) sW[e] = Wb[e];
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (p >= n) return;
+    const int qt = threadIdx.x & 3;
+    const int64_t p = (int64_t)blockIdx.x * (NT / 4) + (threadIdx.x >> 2);
+    const int64_t pc = p < n ? p : 0;
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.f;
-    constexpr int U = 8;                        // inputs whose loads are in flight together
-    for (int i0 = 0; i0 < win; i0 += U) {
-        float zj[U][C];
+    for (int i0 = qt; i0 < win; i0 += 4 * FL_U) {
+        float zj[FL_U][C];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < FL_U; ++u)
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                zj[u][c] = (i0 + u < win) ? zin[((int64_t)c * win + i0 + u) * n + p] : 0.f;
+            for (int c = 0; c < C; ++c) {
+                const int i = i0 + 4 * u;
+                zj[u][c] = i < win ? zin[((int64_t)c * win + i) * n + pc] : 0.f;
+            }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u;
+        for (int u = 0; u < FL_U; ++u) {
+            const int i = i0 + 4 * u;
             if (i >= win) break;
             const float zt = zj[u][0] * inv_w + zoff;
             const int qa = window_k3(zt, nb);
@@ -914,7 +949,11 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
         }
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) out[(int64_t)c * n + p] = acc[c];
+    for (int c = 0; c < C; ++c) acc[c] = quad_sum(acc[c]);
+    if (qt == 0 && p < n) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[(int64_t)c * n + p] = acc[c];
+    }
 }
 
 // zbar[c][i][p] from ubar[c][p]; one thread per (point, input)
@@ -1072,8 +1111,10 @@ static int dw_ii(LayerShape ls, int C)
     return 0;
 }
 
-bool bs32_supported(LayerShape ls)
+bool bs32_supported(LayerShape ls, bool first)
 {
+    // the forward and input-bar kernels take their inputs in whole chunks
+    if (first ? ls.win != 2 : ls.win % 8 != 0) return false;
     if (ls.nb < 4 || ls.nb > 32) return false;
     if (ls.wout == 1) return true;
     if (ls.wout != 32 && ls.wout != 64 && ls.wout != 128) return false;
@@ -1101,7 +1142,7 @@ static int grid_blocks(int64_t tiles, int cap) { return (int)std::max<int64_t>(1
 // BF16 stages nb-1 row pairs of N+4 words per input, input-bar BF16 nb rows
 // of N+8 halfwords, FP32 nb rows of N+4 floats; S = 3 stages the low
 // pieces as well.
-static void w_stage(LayerShape ls, int C, int S, bool fwd, int &KI, size_t &bytes)
+static void w_stage(LayerShape ls, int C, int S, bool fwd, int KJ, int &KI, size_t &bytes)
 {
     size_t per_in;
     if (S == 0)
@@ -1111,7 +1152,7 @@ static void w_stage(LayerShape ls, int C, int S, bool fwd, int &KI, size_t &byte
     else
         per_in = (size_t)ls.nb * (ls.wout + 8) * sizeof(unsigned short);
     if (S == 3) per_in *= 2;
-    const int og = ls.wout / 32;                    // output groups (tiles of 128/og points)
+    const int og = og_of(C, ls.wout / 4);           // output groups (tiles of 128/og points)
     size_t jets = (size_t)KJ * (C + 1) * (TP / og) * sizeof(float);
     if (!fwd && og > 1) jets += (size_t)og * KJ * C * (TP / og) * sizeof(float);
     size_t ki = (LDS_FWD - jets) / per_in;
@@ -1157,14 +1198,16 @@ hipError_t launch_fwd_bs32(ChanCfg ch, bool first, const float *zin, const float
     if (ls.wout == 1) {
         const size_t sh = sizeof(float) * ls.win * ls.nb;
         HRK_CH_SWITCH32(ch, {
-            k_fwd_last<O0, O1><<<(unsigned)((n + NT - 1) / NT), NT, sh, st>>>(zin, W, zout, n, ls.win, g, bm);
+            k_fwd_last<O0, O1><<<(unsigned)((n + NT / 4 - 1) / (NT / 4)), NT, sh, st>>>(zin, W, zout, n, ls.win, g,
+                                                                                    bm);
         });
         return hipGetLastError();
     }
+    if (!bs32_supported(ls, first)) return hipErrorInvalidValue;
     int KI;
     size_t sh;
-    w_stage(ls, ch.C(), S, true, KI, sh);
-    const int tpk = TP / (ls.wout / 32);
+    w_stage(ls, ch.C(), S, true, kj_of(first, ch.C()), KI, sh);
+    const int tpk = TP / og_of(ch.C(), ls.wout / 4);
     const int grid = grid_blocks((n + tpk - 1) / tpk, cu_blocks);
     HRK_CH_S_SWITCH(ch, S, {
         HRK_NQ_SWITCH(ls.wout, {
@@ -1194,10 +1237,11 @@ hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const
         });
         return hipGetLastError();
     }
+    if (!bs32_supported(ls, false)) return hipErrorInvalidValue;
     int KI;
     size_t sh;
-    w_stage(ls, ch.C(), S, false, KI, sh);
-    const int tpk = TP / (ls.wout / 32);
+    w_stage(ls, ch.C(), S, false, kj_of(false, ch.C()), KI, sh);
+    const int tpk = TP / og_of(ch.C(), ls.wout / 4);
     const int grid = grid_blocks((n + tpk - 1) / tpk, cu_blocks);
     HRK_CH_S_SWITCH(ch, S, {
         HRK_NQ_SWITCH(ls.wout, {

@@ -80,7 +80,7 @@ int check_net(const hrkan_net_desc *d, NetInfo *ni)
         if (d->k != 3 || d->m != 4)
             return fail(HRKAN_ERR_UNSUPPORTED, "HRKAN_BF16 needs k = 3 and m = 4 (k=%d, m=%d)", d->k, d->m);
         for (int l = 0; l < d->n_layers; ++l)
-            if (!bs32_supported(LayerShape{d->widths[l], d->widths[l + 1], ni->nb}))
+            if (!bs32_supported(LayerShape{d->widths[l], d->widths[l + 1], ni->nb}, l == 0))
                 return fail(HRKAN_ERR_UNSUPPORTED, "HRKAN_BF16: layer %d shape %d x %d (n_b %d) not supported",
                             l, d->widths[l], d->widths[l + 1], ni->nb);
     }
@@ -136,7 +136,7 @@ int64_t saved_elems(const NetInfo &ni, int C, int64_t n)
 bool use_bs32(const NetInfo &ni, int l)
 {
     return ni.dtype != HRKAN_F64 && ni.m == 4 && ni.k == 3 &&
-           bs32_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb});
+           bs32_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, l == 0);
 }
 
 // BF16 product terms of the matrix-core kernels (0: FP32 products). check_net
