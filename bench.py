@@ -5,8 +5,9 @@ A step is the whole hot path over one batch of synthetic collocation points:
 forward jets at the interior and boundary points, residual and loss, and the
 reverse pass to every weight (hrkan_step). Default workload: viscous Burgers
 (nu = 0.01/pi) with a [2,32,32,1] HRKAN, G = 10, k = 3, m = 4, 65,536 interior
-+ 4,096 initial/boundary points, FP32, inputs resident in HBM, the step
-replayed from a HIP graph.
++ 4,096 initial/boundary points, FP32, inputs resident in HBM; the step is
+timed both launched from the host and replayed from a HIP graph, and the
+faster is reported (the JSON line names it and gives both).
 
 Prints ONE JSON line: interior collocation points per second over the timed
 steps, the roofline position of the dominant kernel (its launches timed with
@@ -123,15 +124,19 @@ def main():
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / k
 
+    # the step launched from the host (its boundary set runs concurrently on a
+    # side stream) and replayed from a HIP graph; the faster is reported
     for _ in range(args.warmup):
         step()
     eager_ms = timed(step, args.steps)
-    ms = eager_ms
+    graph_ms = None
     if not args.eager:
         step.capture()
         for _ in range(args.warmup):
             step.replay()
-        ms = timed(step.replay, args.steps)
+        graph_ms = timed(step.replay, args.steps)
+    launch = "hip_graph" if graph_ms is not None and graph_ms < eager_ms else "eager"
+    ms = graph_ms if launch == "hip_graph" else eager_ms
     loss = step.loss.cpu().numpy()
 
     # per-kernel times: HIP events around every launch, on its own stream
@@ -208,8 +213,9 @@ def main():
             "n_int": pr.n_int, "n_bc": pr.n_bc,
             **({"bf16_split": args.bf16_split} if dtype == "bf16" else {}),
         },
-        "launch": "eager" if args.eager else "hip_graph",
+        "launch": launch,
         "eager_ms_per_step": round(eager_ms, 5),
+        "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 5),
         "total_points_per_s": round((pr.n_int + pr.n_bc) / (ms * 1e-3), 1),
         "step_dense_tflops": round(step_flops / (ms * 1e-3) / 1e12, 3),
         "loss": [float(v) for v in loss],

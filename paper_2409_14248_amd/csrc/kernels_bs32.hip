@@ -733,39 +733,70 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
     for (int e = threadIdx.x; e < IB * IS; e += NT) sG[e] = 0.f;
     float *gbase = sG + (wp * IBe + ii) * IS + 4 * jc + s;
 
+    // staging: each thread's loads of a chunk start at fixed offsets from the
+    // chunk's first point (computed once); LDS targets likewise
+    const float *jsrc[RJ];
+    int jdst[RJ], jpp[RJ];
+    bool jok[RJ];
+#pragma unroll
+    for (int k = 0; k < RJ; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int pp = e % PC, rest = e / PC, il = rest % IB, c = rest / IB;
+        jok[k] = e < EJ && il < IBe && i0 + il < win;
+        const int ic = jok[k] ? i0 + il : 0;
+        jpp[k] = pp;
+        jdst[k] = pp * JS + il * CP + c;
+        if constexpr (FIRST)
+            jsrc[k] = zin + 2 * (int64_t)pp + ic;            // x[2p + i]; channel c from input_jets
+        else
+            jsrc[k] = zin + (int64_t)((jok[k] ? c : 0) * win + ic) * n + pp;
+    }
+    const float *ysrc[RY];
+    int ydst[RY], ypp[RY];
+    bool yok[RY];
+#pragma unroll
+    for (int k = 0; k < RY; ++k) {
+        const int e = threadIdx.x + k * NT;
+        const int pp = e % PC, rest = e / PC, j = rest % N, c = rest / N;
+        yok[k] = e < EY;
+        ypp[k] = pp;
+        ydst[k] = pp * YS + j * CP + c;
+        ysrc[k] = ybar + (int64_t)((yok[k] ? c : 0) * N + (yok[k] ? j : 0)) * n + pp;
+    }
     float rj[RJ], ry[RY];
     auto load = [&](int64_t pc) {
 #pragma unroll
         for (int k = 0; k < RJ; ++k) {
-            const int e = threadIdx.x + k * NT;
-            const int pp = e % PC, rest = e / PC, il = rest % IB, c = rest / IB;
-            const int64_t p = pc + pp;
-            const bool ok = e < EJ && p < pe && il < IBe && i0 + il < win;
-            const int ic = ok ? i0 + il : 0;
-            const int64_t pq = ok ? p : 0;
+            const bool ok = jok[k] && pc + jpp[k] < pe;
+            const int64_t o = ok ? pc : -(int64_t)jpp[k];   // a dead lane reads its row's first element
             float v;
             if constexpr (FIRST) {
+                // input layer: jets of x_i are (x_i, d/dx0 = [i == 0], ..., d/dx1 = [i == 1], ...)
+                const int e = threadIdx.x + k * NT;
+                const int rest = e / PC, il = rest % IB, c = rest / IB;
                 float zj[C];
-                input_jets<float, O0, O1>(zin, pq, ic, zj);
-                v = zj[c];
+                input_jets<float, O0, O1>(zin, ok ? pc + jpp[k] : 0, ok ? i0 + il : 0, zj);
+                v = zj[c < C ? c : 0];
             } else {
-                v = zin[(int64_t)(c * win + ic) * n + pq];
+                v = jsrc[k][o];
             }
             rj[k] = ok ? v : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
-            const int e = threadIdx.x + k * NT;
-            const int pp = e % PC, rest = e / PC, j = rest % N, c = rest / N;
-            const int64_t p = pc + pp;
-            const bool ok = e < EY && p < pe;
-            const float y = ybar[(int64_t)((ok ? c : 0) * N + (ok ? j : 0)) * n + (ok ? p : 0)];
+            const bool ok = yok[k] && pc + ypp[k] < pe;
+            const float y = ysrc[k][ok ? pc : -(int64_t)ypp[k]];
             ry[k] = ok ? y : 0.f;
         }
     };
-    // products of point pp for this lane's input: d[pass][t] (column s); the
-    // passes are interleaved so that consecutive MFMAs are independent
-    auto products = [&](int pp, f4 *d) -> int {
+    // one point's operands for this lane's input: window, features (row t = s)
+    // and the output bars of this lane's columns
+    struct Pt {
+        int qa;
+        float A[C];
+        float yv[PASSES][CP];
+    };
+    auto prepare = [&](int pp, Pt &o) {
         float zj[CP];
 #pragma unroll
         for (int c4 = 0; c4 < CP / 4; ++c4) {
@@ -773,27 +804,41 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
             zj[4 * c4 + 0] = z4[0]; zj[4 * c4 + 1] = z4[1]; zj[4 * c4 + 2] = z4[2]; zj[4 * c4 + 3] = z4[3];
         }
         const float zt = zj[0] * inv_w + zoff;
-        const int qa = window_k3(zt, nb);
-        float v[3], A[C];
-        bump_k3m4<2>(zt, qa + s, inv_w, v);      // this lane's row: window row t = s
-        features<float, O0, O1>(v, zj, A);
-        float yv[PASSES][CP];
+        o.qa = window_k3(zt, nb);
+        float v[3];
+        bump_k3m4<2>(zt, o.qa + s, inv_w, v);
+        features<float, O0, O1>(v, zj, o.A);
 #pragma unroll
         for (int q = 0; q < PASSES; ++q)
 #pragma unroll
             for (int c4 = 0; c4 < CP / 4; ++c4) {
                 const f4 y4 = *reinterpret_cast<const f4 *>(sY + pp * YS + (4 * (q * JC + jc) + s) * CP + 4 * c4);
-                yv[q][4 * c4 + 0] = y4[0]; yv[q][4 * c4 + 1] = y4[1];
-                yv[q][4 * c4 + 2] = y4[2]; yv[q][4 * c4 + 3] = y4[3];
+                o.yv[q][4 * c4 + 0] = y4[0]; o.yv[q][4 * c4 + 1] = y4[1];
+                o.yv[q][4 * c4 + 2] = y4[2]; o.yv[q][4 * c4 + 3] = y4[3];
             }
+    };
+    // rows qa..qa+3 of this lane's input: the stored sums enter the MFMAs as
+    // accumulators (no separate additions) and the results are written back;
+    // the passes are interleaved so that consecutive MFMAs are independent
+    auto rd = [&](const float *gp, f4 *d) {
 #pragma unroll
-        for (int q = 0; q < PASSES; ++q) d[q] = (f4){0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < PASSES; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[q][r] = gp[r * GS + 4 * q * JC];
+    };
+    auto wr = [&](float *gp, const f4 *d) {
+#pragma unroll
+        for (int q = 0; q < PASSES; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gp[r * GS + 4 * q * JC] = d[q][r];
+    };
+    auto mm = [&](const Pt &o, f4 *d) {
         if constexpr (S == 0) {
 #pragma unroll
             for (int c = 0; c < C; ++c)
 #pragma unroll
                 for (int q = 0; q < PASSES; ++q)
-                    d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[c], yv[q][c], d[q], 0, 0, 0);
+                    d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.A[c], o.yv[q][c], d[q], 0, 0, 0);
         } else {
             // K = 4 channels per 4x4x4 MFMA (channels beyond C are zero)
             constexpr int CG = CP / 4;
@@ -802,7 +847,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
             for (int g4 = 0; g4 < CG; ++g4) {
                 float a4[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) a4[e] = (4 * g4 + e < C) ? A[(4 * g4 + e) < C ? 4 * g4 + e : 0] : 0.f;
+                for (int e = 0; e < 4; ++e) a4[e] = (4 * g4 + e < C) ? o.A[(4 * g4 + e) < C ? 4 * g4 + e : 0] : 0.f;
                 if constexpr (S >= 2)
                     split4(a4, fh[g4], fl[g4]);
                 else
@@ -814,7 +859,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
                 for (int q = 0; q < PASSES; ++q) {
                     float y4[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) y4[e] = (4 * g4 + e < C) ? yv[q][4 * g4 + e] : 0.f;
+                    for (int e = 0; e < 4; ++e) y4[e] = (4 * g4 + e < C) ? o.yv[q][4 * g4 + e] : 0.f;
                     s4 yh, yl;
                     if constexpr (S == 3)
                         split4(y4, yh, yl);
@@ -825,52 +870,39 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
                     if constexpr (S == 3) d[q] = mfma_bf16(fh[g4], yl, d[q]);
                 }
         }
-        return qa;
     };
-    // rows qa..qa+3 of this lane's input: all reads, then all writes
-    auto accumulate = [&](int qa, const f4 *d) {
-        float *gp = gbase + qa * GS;
-        float old[PASSES][4];
-#pragma unroll
-        for (int q = 0; q < PASSES; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) old[q][r] = gp[r * GS + 4 * q * JC];
-#pragma unroll
-        for (int q = 0; q < PASSES; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) gp[r * GS + 4 * q * JC] = old[q][r] + d[q][r];
+    auto update = [&](const Pt &o) {
+        f4 d[PASSES];
+        float *g = gbase + o.qa * GS;
+        rd(g, d);
+        mm(o, d);
+        wr(g, d);
     };
 
     if (ps < pe) load(ps);
     for (int64_t pc = ps; pc < pe; pc += PC) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < RJ; ++k) {
-            const int e = threadIdx.x + k * NT;
-            const int pp = e % PC, rest = e / PC, il = rest % IB, c = rest / IB;
-            if (e < EJ) sJ[pp * JS + il * CP + c] = rj[k];
-        }
+        for (int k = 0; k < RJ; ++k)
+            if (threadIdx.x + k * NT < EJ) sJ[jdst[k]] = rj[k];
 #pragma unroll
-        for (int k = 0; k < RY; ++k) {
-            const int e = threadIdx.x + k * NT;
-            const int pp = e % PC, rest = e / PC, j = rest % N, c = rest / N;
-            if (e < EY) sY[pp * YS + j * CP + c] = ry[k];
-        }
+        for (int k = 0; k < RY; ++k)
+            if (threadIdx.x + k * NT < EY) sY[ydst[k]] = ry[k];
         __syncthreads();
         if (pc + PC < pe) load(pc + PC);         // next chunk in flight during this one
         const int npts = (int)min<int64_t>(PC, pe - pc);
         int pp = wp;
         for (; pp + WP < npts; pp += 2 * WP) {
-            f4 d0[PASSES], d1[PASSES];
-            const int q0 = products(pp, d0);
-            const int q1 = products(pp + WP, d1);
-            accumulate(q0, d0);
-            accumulate(q1, d1);
+            Pt a, b;
+            prepare(pp, a);
+            prepare(pp + WP, b);
+            update(a);
+            update(b);
         }
         if (pp < npts) {
-            f4 d0[PASSES];
-            const int q0 = products(pp, d0);
-            accumulate(q0, d0);
+            Pt a;
+            prepare(pp, a);
+            update(a);
         }
     }
     __syncthreads();
