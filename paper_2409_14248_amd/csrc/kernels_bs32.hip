@@ -52,14 +52,14 @@ template <int O0, int O1, int NQ> constexpr int fwd_waves() { return Ch<O0, O1>:
 template <int T>
 __device__ __forceinline__ float qbcast(float v)
 {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), T * 0x55, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), T * 0x55, 0xF, 0xF, true));
 }
 
 // Sum over the 4 lanes of each quad (result in every lane of the quad).
 __device__ __forceinline__ float quad_sum(float v)
 {
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
     return v;
 }
 
@@ -470,9 +470,9 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_fwd_bs(const
 // the adjoint of the features through v..v''' gives zbar[.][i][p].
 // Block row = channel, block column = window row t. S = 0: FP32, K = one
 // output per 4x4x1 MFMA; S > 0: BF16, K = 4 outputs per 4x4x4 MFMA, the
-// bars split once per tile and the weights staged as BF16 rows. Even and odd
-// output quads accumulate in separate chains so consecutive MFMAs are
-// independent.
+// bars split once per tile and the weights staged as BF16 rows. Output quads
+// accumulate in up to 4 separate chains (added in order at the end) so
+// consecutive MFMAs are independent.
 // ---------------------------------------------------------------------------
 template <int O0, int O1, int NQ, int S>
 __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const float *__restrict__ zin,
@@ -585,9 +585,10 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
             for (int c = 0; c < C; ++c) zj[c] = zc[c * TPK];
             const float zt = zj[0] * inv_w + zoff;
             const int qa = window_k3(zt, nb);
-            f4 ab[2][RG];       // two accumulation chains: even / odd output quads
+            constexpr int NCH = S == 0 ? 4 : (NQW >= 4 ? 4 : NQW);   // independent accumulation chains
+            f4 ab[NCH][RG];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < NCH; ++h)
 #pragma unroll
                 for (int r = 0; r < RG; ++r) ab[h][r] = (f4){0.f, 0.f, 0.f, 0.f};
             if constexpr (S == 0) {
@@ -600,8 +601,8 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
                     for (int e = 0; e < 4; ++e)
 #pragma unroll
                         for (int r = 0; r < RG; ++r)
-                            ab[j4 & 1][r] = __builtin_amdgcn_mfma_f32_4x4x1f32(yb[r][4 * j4 + e], w4[e],
-                                                                               ab[j4 & 1][r], 0, 0, 0);
+                            ab[e % NCH][r] = __builtin_amdgcn_mfma_f32_4x4x1f32(yb[r][4 * j4 + e], w4[e],
+                                                                                ab[e % NCH][r], 0, 0, 0);
                 }
             } else {
                 const int hrow = ((i - iW) * nb + qa + s) * NSH + jb;
@@ -613,7 +614,7 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
                         wl = __builtin_bit_cast(s4, *reinterpret_cast<const u2 *>(sHl + hrow + 4 * j4));
 #pragma unroll
                     for (int r = 0; r < RG; ++r) {
-                        f4 &a = ab[j4 & 1][r];
+                        f4 &a = ab[j4 % NCH][r];
                         a = mfma_bf16(ybp[r][j4][0], wh, a);
                         if constexpr (S >= 2) a = mfma_bf16(ybp[r][j4][SA - 1], wh, a);
                         if constexpr (S == 3) a = mfma_bf16(ybp[r][j4][0], wl, a);
@@ -625,7 +626,12 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
             bump_k3m4<3>(zt, qa + s, inv_w, v);
             float Ab[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) Ab[c] = ab[0][c / 4][c % 4] + ab[1][c / 4][c % 4];
+            for (int c = 0; c < C; ++c) {
+                float t = ab[0][c / 4][c % 4];
+#pragma unroll
+                for (int h = 1; h < NCH; ++h) t += ab[h][c / 4][c % 4];
+                Ab[c] = t;
+            }
             float zb[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) zb[c] = 0.f;
@@ -681,10 +687,11 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
 // N outputs of one slice; the next chunk of points is loaded while the
 // current one is computed.
 // ---------------------------------------------------------------------------
-// points per staged chunk: wide layers 8 (LDS), 2-input-per-wave tiles of
-// 32-output layers 64 (short per-point work: fewer, larger chunks keep the
-// global loads ahead of the compute), else 16
-template <int NQ, int II> constexpr int dw_pc() { return NQ >= 32 ? 8 : (II == 2 && NQ <= 8) ? 64 : 16; }
+// points per staged chunk (a divisor of the block size): short per-point
+// work (2 inputs per wave) takes large chunks so the global loads stay ahead
+// of the compute -- 64 points for 32-output layers; else 16, or 8 for wide
+// 5-channel tiles (LDS)
+template <int NQ, int II, int C> constexpr int dw_pc() { return NQ >= 32 ? ((II == 2 && C <= 4) ? 16 : 8) : (II == 2 && NQ <= 8) ? 64 : 16; }
 
 template <int O0, int O1, bool FIRST, int NQ, int II, int S>
 __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
@@ -702,7 +709,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
     constexpr int IB = 4 * II;               // staged inputs (WI * II of them real)
     constexpr int JC = 16 / II;              // 4-output chunks per MFMA
     constexpr int PASSES = NQ / JC;
-    constexpr int PC = dw_pc<NQ, II>();
+    constexpr int PC = dw_pc<NQ, II, C>();
     constexpr int JS = IB * CP + 4;          // staged jets: stride per point
     constexpr int YS = N * CP + 4;           // staged bars: stride per point
     constexpr int EJ = C * IB * PC, EY = C * N * PC;
@@ -751,18 +758,13 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         else
             jsrc[k] = zin + (int64_t)((jok[k] ? c : 0) * win + ic) * n + pp;
     }
-    const float *ysrc[RY];
-    int ydst[RY], ypp[RY];
-    bool yok[RY];
-#pragma unroll
-    for (int k = 0; k < RY; ++k) {
-        const int e = threadIdx.x + k * NT;
-        const int pp = e % PC, rest = e / PC, j = rest % N, c = rest / N;
-        yok[k] = e < EY;
-        ypp[k] = pp;
-        ydst[k] = pp * YS + j * CP + c;
-        ysrc[k] = ybar + (int64_t)((yok[k] ? c : 0) * N + (yok[k] ? j : 0)) * n + pp;
-    }
+    // bars: element e = threadIdx.x + k NT is point pp = e % PC (the same for
+    // every k, PC dividing NT) of row e / PC = c N + j, so the k-th load is
+    // the first one plus k (NT / PC) rows
+    static_assert(NT % PC == 0, "chunk size must divide the block");
+    const int ypp = threadIdx.x % PC, yrow0 = threadIdx.x / PC;
+    const float *ysrc = ybar + (int64_t)yrow0 * n + ypp;
+    const int64_t ystep = (int64_t)(NT / PC) * n;
     float rj[RJ], ry[RY];
     auto load = [&](int64_t pc) {
 #pragma unroll
@@ -782,10 +784,11 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
             }
             rj[k] = ok ? v : 0.f;
         }
+        const bool yin = pc + ypp < pe;
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
-            const bool ok = yok[k] && pc + ypp[k] < pe;
-            const float y = ysrc[k][ok ? pc : -(int64_t)ypp[k]];
+            const bool ok = yin && threadIdx.x + k * NT < EY;
+            const float y = ysrc[ok ? k * ystep + pc : -(int64_t)ypp];   // a dead lane reads its first row
             ry[k] = ok ? y : 0.f;
         }
     };
@@ -886,8 +889,10 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         for (int k = 0; k < RJ; ++k)
             if (threadIdx.x + k * NT < EJ) sJ[jdst[k]] = rj[k];
 #pragma unroll
-        for (int k = 0; k < RY; ++k)
-            if (threadIdx.x + k * NT < EY) sY[ydst[k]] = ry[k];
+        for (int k = 0; k < RY; ++k) {
+            const int row = yrow0 + k * (NT / PC), j = row % N, c = row / N;
+            if (threadIdx.x + k * NT < EY) sY[ypp * YS + j * CP + c] = ry[k];
+        }
         __syncthreads();
         if (pc + PC < pe) load(pc + PC);         // next chunk in flight during this one
         const int npts = (int)min<int64_t>(PC, pe - pc);
@@ -922,7 +927,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
 static size_t dw_bs_lds(int C, int nb, int N, int II)
 {
     const int CP = C <= 4 ? 4 : 8, IB = 4 * II, JC = 16 / II;
-    const int PC = N >= 128 ? 8 : (II == 2 && N <= 32) ? 64 : 16;
+    const int PC = N >= 128 ? ((II == 2 && C <= 4) ? 16 : 8) : (II == 2 && N <= 32) ? 64 : 16;
     return sizeof(float) *
            ((size_t)IB * (nb * N + 4 * JC) + (size_t)PC * (IB * CP + 4) + (size_t)PC * (N * CP + 4));
 }
