@@ -15,6 +15,7 @@
 #include "hrkan.h"
 #include "internal.h"
 #include "kernels_bs.h"
+#include "kernels_dn.h"
 #include "runtime_internal.h"
 
 namespace hrk {
@@ -122,7 +123,7 @@ GridP<T> make_grid(const NetInfo &ni)
 template GridP<float> make_grid<float>(const NetInfo &);
 template GridP<double> make_grid<double>(const NetInfo &);
 
-static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int64_t saved_elems(const NetInfo &ni, int C, int64_t n)
 {
@@ -140,6 +141,40 @@ bool use_bs32(const NetInfo &ni, int l)
            bs32_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, l == 0);
 }
 
+// Hidden BF16 layers with 32, 64 or 128 outputs run on the dense BF16
+// kernels (HRKAN_BF16_DENSE=0 in the environment keeps them on the
+// block-sparse ones); the input and output layers stay block-sparse.
+bool use_dn(const NetInfo &ni, int l)
+{
+    static const bool enabled = [] {
+        const char *e = getenv("HRKAN_BF16_DENSE");
+        return !(e && e[0] == '0');
+    }();
+    return enabled && ni.dtype == HRKAN_BF16 && ni.m == 4 && ni.k == 3 &&
+           dn_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, l == 0);
+}
+
+
+size_t wdn_offset(const NetInfo &ni, int l)
+{
+    size_t o = 0;
+    for (int q = 0; q < l; ++q)
+        if (use_dn(ni, q)) o += up256(dn_w_bytes(LayerShape{ni.w[q], ni.w[q + 1], ni.nb}, ni.S));
+    return o;
+}
+
+// The padded BF16 weight copies the dense kernels read, for every such layer.
+int prep_dense(const NetInfo &ni, const float *const *W, char *wdn, hipStream_t st)
+{
+    for (int l = 0; l < ni.L; ++l) {
+        if (!use_dn(ni, l)) continue;
+        const hipError_t e =
+            launch_w_prep_dn(W[l], wdn + wdn_offset(ni, l), LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, ni.S, st);
+        if (e != hipSuccess) return hip_fail(e, "weight copy launch");
+    }
+    return HRKAN_OK;
+}
+
 // BF16 product terms of the matrix-core kernels (0: FP32 products). check_net
 // admits HRKAN_BF16 only where every layer runs on them.
 int bf16_terms(const NetInfo &ni) { return ni.dtype == HRKAN_BF16 ? ni.S : 0; }
@@ -148,6 +183,7 @@ int dw_splits(const NetInfo &ni, int l, int64_t n)
 {
     if (n <= 0) return 0;
     const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
+    if (use_dn(ni, l)) return dw_dn_splits(n, ls);
     return use_bs32(ni, l) ? dw_bs32_splits(n, ls) : dw_generic_splits(n, ls);
 }
 
@@ -258,6 +294,7 @@ WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
     L.bbars1 = take(E * (size_t)ni.maxw * n_bc);
     L.part_elems = part_elems_total(ni, n_int, n_bc);
     L.part = take(E * (size_t)L.part_elems);
+    L.wdn = take(wdn_offset(ni, ni.L));
     L.total = o;
     return L;
 }
@@ -285,7 +322,8 @@ namespace {
 
 template <typename T>
 int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, int64_t n,
-                 T *jets_out, T *saved, T *tmp0, T *tmp1, hipStream_t st, bool bc = false)
+                 T *jets_out, T *saved, T *tmp0, T *tmp1, hipStream_t st, bool bc = false,
+                 const char *wdn = nullptr)
 {
     const GridP<T> g = make_grid<T>(ni);
     const int C = ch.C();
@@ -305,7 +343,9 @@ int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, i
             ProfScope ps("fwd", l, st, bc);
             const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
             if constexpr (std::is_same<T, float>::value) {
-                if (use_bs32(ni, l))
+                if (use_dn(ni, l))
+                    e = launch_fwd_dn(ch, zin, wdn + wdn_offset(ni, l), zout, n, ls, g, ni.S, st);
+                else if (use_bs32(ni, l))
                     e = launch_fwd_bs32(ch, l == 0, zin, W[l], zout, n, ls, g, cu_blocks(), bf16_terms(ni), st);
                 else
                     e = launch_fwd_generic<T>(ch, l == 0, zin, W[l], zout, n, ls, g, st);
@@ -354,7 +394,7 @@ struct RevSet {
 
 template <typename T>
 int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const int64_t *off, T *part,
-                hipStream_t st, bool bc)
+                hipStream_t st, bool bc, const char *wdn)
 {
     const GridP<T> g = make_grid<T>(ni);
     const T *ybar = S.seed;
@@ -367,7 +407,9 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             ProfScope ps("dw", l, st, bc);
             T *dst = part + off[l];
             if constexpr (std::is_same<T, float>::value) {
-                if (use_bs32(ni, l))
+                if (use_dn(ni, l))
+                    e = launch_dw_dn(S.ch, zin, ybar, dst, ns, S.n, ls, g, ni.S, st);
+                else if (use_bs32(ni, l))
                     e = launch_dw_bs32(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, bf16_terms(ni), st);
                 else
                     e = launch_dw_generic<T>(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, st);
@@ -381,7 +423,9 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
         {
             ProfScope ps("dx", l, st, bc);
             if constexpr (std::is_same<T, float>::value) {
-                if (use_bs32(ni, l))
+                if (use_dn(ni, l))
+                    e = launch_dx_dn(S.ch, zin, ybar, wdn + wdn_offset(ni, l), zbar, S.n, ls, g, ni.S, st);
+                else if (use_bs32(ni, l))
                     e = launch_dx_bs32(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, cu_blocks(), bf16_terms(ni), st);
                 else
                     e = launch_dx_generic<T>(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, st);
@@ -401,7 +445,7 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
 // element summed over its slices in that fixed order.
 template <typename T>
 int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, int nsets,
-                 T *const *gW, int accumulate, T *part, hipStream_t st, Fork *fk)
+                 T *const *gW, int accumulate, T *part, hipStream_t st, Fork *fk, const char *wdn)
 {
     const int64_t n0 = nsets > 0 ? sets[0].n : 0, n1 = nsets > 1 ? sets[1].n : 0;
     int64_t base[HRKAN_MAX_LAYERS], off0[HRKAN_MAX_LAYERS], off1[HRKAN_MAX_LAYERS];
@@ -418,8 +462,8 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
     }
     const bool split = fk && n0 > 0 && n1 > 0;
     if (split) TRY(fork_to(fk, st));
-    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st, true));
-    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false));
+    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st, true, wdn));
+    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false, wdn));
     if (split) TRY(join_from(fk, st));
     for (int l = ni.L - 1; l >= 0; --l) {
         const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
@@ -558,9 +602,10 @@ int hrkan_forward_jets(const hrkan_net_desc *net, const void *const *W, const vo
         return forward_impl<double>(ni, ch, (const double *const *)W, (const double *)x, n,
                                     (double *)jets_out, (double *)saved, (double *)(w + L.bars0),
                                     (double *)(w + L.bars1), stream);
+    TRY(prep_dense(ni, (const float *const *)W, w + L.wdn, stream));
     return forward_impl<float>(ni, ch, (const float *const *)W, (const float *)x, n,
                                (float *)jets_out, (float *)saved, (float *)(w + L.bars0),
-                               (float *)(w + L.bars1), stream);
+                               (float *)(w + L.bars1), stream, false, w + L.wdn);
 }
 
 int hrkan_residual(const hrkan_pde_desc *pde, int32_t dtype, const void *jets_int, const void *u_bc,
@@ -621,12 +666,13 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
         RevSet<double> s{ch, (const double *)x, n, (const double *)seed, (const double *)saved,
                          (double *)(w + L.bars0), (double *)(w + L.bars1)};
         return reverse_impl<double>(ni, (const double *const *)W, &s, 1, (double *const *)gW_out,
-                                    accumulate, (double *)(w + L.part), stream, nullptr);
+                                    accumulate, (double *)(w + L.part), stream, nullptr, nullptr);
     }
     RevSet<float> s{ch, (const float *)x, n, (const float *)seed, (const float *)saved,
                     (float *)(w + L.bars0), (float *)(w + L.bars1)};
+    if (n > 0) TRY(prep_dense(ni, (const float *const *)W, w + L.wdn, stream));
     return reverse_impl<float>(ni, (const float *const *)W, &s, 1, (float *const *)gW_out, accumulate,
-                               (float *)(w + L.part), stream, nullptr);
+                               (float *)(w + L.part), stream, nullptr, w + L.wdn);
 }
 
 int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
@@ -662,15 +708,18 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         T *sv_bc = (T *)(w + L.sv_bc), *ubc = (T *)(w + L.ubc);
         T *seed_int = (T *)(w + L.seed_int), *seed_bc = (T *)(w + L.seed_bc);
         // boundary set on the side stream, interior set on the caller's
+        char *wdn = w + L.wdn;
+        if constexpr (std::is_same<T, float>::value)
+            if (ni_ + nb_ > 0) TRY(prep_dense(ni, (const float *const *)W, wdn, stream));
         Fork *fk = nullptr;
         if (ni_ > 0 && nb_ > 0) TRY(get_fork(stream, &fk));
         if (fk) TRY(fork_to(fk, stream));
         if (nb_ > 0)
             TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
-                                nullptr, nullptr, fk ? fk->side : stream, true));
+                                nullptr, nullptr, fk ? fk->side : stream, true, wdn));
         if (ni_ > 0)
             TRY(forward_impl<T>(ni, chi, (const T *const *)W, (const T *)pts->x_int, ni_, jets, sv_int,
-                                nullptr, nullptr, stream));
+                                nullptr, nullptr, stream, false, wdn));
         if (fk) TRY(join_from(fk, stream));
         double *partials = (double *)(w + L.loss_part);
         hipError_t e;
@@ -692,7 +741,7 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
             {chb, (const T *)pts->x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
         };
         return reverse_impl<T>(ni, (const T *const *)W, sets, 2, (T *const *)gW_out, 0,
-                               (T *)(w + L.part), stream, fk);
+                               (T *)(w + L.part), stream, fk, wdn);
     };
     if (ni.dtype == HRKAN_F64) return run(double{});
     return run(float{});

@@ -26,6 +26,7 @@ struct NetInfo {
 struct WsLayout {
     size_t status, loss_part, sv_int, jets_int, sv_bc, ubc, seed_int, seed_bc;
     size_t bars0, bars1, bbars0, bbars1, part;
+    size_t wdn;                 // BF16 weight copies of the dense-kernel layers
     int64_t part_elems;
     int nres;
     size_t total;
@@ -51,6 +52,9 @@ int get_fork(hipStream_t st, Fork **out);
 int fork_to(Fork *f, hipStream_t st);      // side waits for st's work so far
 int join_from(Fork *f, hipStream_t st);    // st waits for side's work so far
 bool use_bs32(const NetInfo &ni, int l);
+bool use_dn(const NetInfo &ni, int l);
+size_t wdn_offset(const NetInfo &ni, int l);   // layer l's copies within the wdn region
+int prep_dense(const NetInfo &ni, const float *const *W, char *wdn, hipStream_t st);
 int bf16_terms(const NetInfo &ni);
 int cu_blocks();
 WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc);
