@@ -44,8 +44,7 @@ typedef unsigned short hw;   // the bits of one BF16 value
 
 constexpr int DN_T = 512;    // forward / input-bar block: 8 waves of 16 points
 constexpr int DN_P = 128;    // points per forward / input-bar block
-constexpr int DW_T = 512;    // weight-gradient block: 8 waves of 3 row tiles
-constexpr int DW_R = 384;    // padded gradient rows per weight-gradient block
+constexpr int DW_T = 512;    // weight-gradient block: 8 waves of 2 inputs each
 constexpr int DN_LDS_MAX = 160 * 1024;
 
 __device__ __forceinline__ unsigned int pk2(float a, float b)
@@ -132,7 +131,7 @@ __device__ __forceinline__ void dn_features(const float *s, float cb, float *A)
 
 // ---------------------------------------------------------------------------
 // weight copies: W [win * nb][N] FP32 -> Wr [kpad][N], Wt [N][kpad] BF16
-// (padded rows zero), low pieces into Wrl / Wtl when those are given
+// (padded rows zero), low pieces into Wrl / Wtl where those are given
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_w_prep(const float *__restrict__ W, hw *__restrict__ Wr,
                                                 hw *__restrict__ Wt, hw *__restrict__ Wrl,
@@ -147,11 +146,9 @@ __global__ __launch_bounds__(256) void k_w_prep(const float *__restrict__ W, hw 
     const unsigned int h = pk2(v, 0.f);
     Wr[(int64_t)kk * N + j] = (hw)h;
     Wt[(int64_t)j * kpad + kk] = (hw)h;
-    if (Wrl) {
-        const hw l = (hw)pk2(v - lo_f(h), 0.f);
-        Wrl[(int64_t)kk * N + j] = l;
-        Wtl[(int64_t)j * kpad + kk] = l;
-    }
+    const hw l = (hw)pk2(v - lo_f(h), 0.f);
+    if (Wrl) Wrl[(int64_t)kk * N + j] = l;
+    if (Wtl) Wtl[(int64_t)j * kpad + kk] = l;
 }
 
 // ---------------------------------------------------------------------------
@@ -190,7 +187,7 @@ __global__ __launch_bounds__(DN_T) void k_fwd_dn(const float *__restrict__ zin, 
     static_assert(4 * DN_P == DN_T, "one staged (point, input) pair per thread");
     extern __shared__ __align__(16) float smem[];
     hw *sW = reinterpret_cast<hw *>(smem);                         // [2][NWP][N][RS]
-    float *sJ = smem + (2 * NWP * WEL) / 2;                        // [2][4][DN_P][8]
+    float *sJ = smem + (2 * NWP * WEL) / 2;                        // [2][2 planes][4][DN_P][4]
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -230,9 +227,11 @@ __global__ __launch_bounds__(DN_T) void k_fwd_dn(const float *__restrict__ zin, 
         }
         float s[8];
         scale_jets<O0, O1>(rj, inv_w, zoff, s);
-        float *d = sJ + (size_t)buf * F::JEL + (sj_il * DN_P + sj_pp) * 8;
+        // slots 0..3 and 4..7 in separate planes: consecutive lanes read
+        // consecutive 16-byte words
+        float *d = sJ + (size_t)buf * F::JEL + (sj_il * DN_P + sj_pp) * 4;
         *reinterpret_cast<f4 *>(d) = (f4){s[0], s[1], s[2], s[3]};
-        *reinterpret_cast<f4 *>(d + 4) = (f4){s[4], s[5], s[6], s[7]};
+        *reinterpret_cast<f4 *>(d + F::JEL / 2) = (f4){s[4], s[5], s[6], s[7]};
     };
 
     f4 acc[C][NQ];
@@ -253,8 +252,8 @@ __global__ __launch_bounds__(DN_T) void k_fwd_dn(const float *__restrict__ zin, 
         for (int ks = 0; ks < KS; ++ks) {
             const int G = 4 * ks + g;              // this lane's 8-row group in the chunk
             const int il = G / GPI, b0 = 8 * (G % GPI);
-            const float *sp = J0 + (il * DN_P + wv * 16 + r16) * 8;
-            const f4 s0 = *reinterpret_cast<const f4 *>(sp), s1 = *reinterpret_cast<const f4 *>(sp + 4);
+            const float *sp = J0 + (il * DN_P + wv * 16 + r16) * 4;
+            const f4 s0 = *reinterpret_cast<const f4 *>(sp), s1 = *reinterpret_cast<const f4 *>(sp + F::JEL / 2);
             const float s[8] = {s0[0], s0[1], s0[2], s0[3], s1[0], s1[1], s1[2], s1[3]};
             const float cb0 = 1.5f - 0.5f * (float)b0;
             float A[C][8];
@@ -279,12 +278,15 @@ __global__ __launch_bounds__(DN_T) void k_fwd_dn(const float *__restrict__ zin, 
                 const bf8 bh = *reinterpret_cast<const bf8 *>(W0 + o);
                 bf8 bl;
                 if constexpr (S == 3) bl = *reinterpret_cast<const bf8 *>(W0 + WEL + o);
+                // consecutive products go to different accumulators
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    acc[c][q] = mfma(ah[c], bh, acc[c][q]);
-                    if constexpr (S >= 2) acc[c][q] = mfma(al[c], bh, acc[c][q]);
-                    if constexpr (S == 3) acc[c][q] = mfma(ah[c], bl, acc[c][q]);
-                }
+                for (int c = 0; c < C; ++c) acc[c][q] = mfma(ah[c], bh, acc[c][q]);
+                if constexpr (S >= 2)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c][q] = mfma(al[c], bh, acc[c][q]);
+                if constexpr (S == 3)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c][q] = mfma(ah[c], bl, acc[c][q]);
             }
         }
         if (ci + 1 < nch) store(buf ^ 1);
@@ -432,11 +434,13 @@ __global__ __launch_bounds__(DN_T) void k_dx_dn(const float *__restrict__ zin, c
                 bf8 al;
                 if constexpr (S == 3) al = *reinterpret_cast<const bf8 *>(W0 + WEL + o);
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    acc[c] = mfma(ah, yh[c][ks], acc[c]);
-                    if constexpr (S >= 2) acc[c] = mfma(ah, yl[c][ks], acc[c]);
-                    if constexpr (S == 3) acc[c] = mfma(al, yh[c][ks], acc[c]);
-                }
+                for (int c = 0; c < C; ++c) acc[c] = mfma(ah, yh[c][ks], acc[c]);
+                if constexpr (S >= 2)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] = mfma(ah, yl[c][ks], acc[c]);
+                if constexpr (S == 3)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] = mfma(al, yh[c][ks], acc[c]);
             }
             // rows 16 t + 4 g + r of the chunk: input h, basis rows b0 + r
             const int row0 = 16 * t + 4 * g;
@@ -530,12 +534,14 @@ __global__ __launch_bounds__(DN_T) void k_dx_dn(const float *__restrict__ zin, c
 // ---------------------------------------------------------------------------
 // weight gradient: part[split][i nb + b][j] = sum over the slice's points
 // and channels of A_c[p][i, b] ybar_c[j][p]; MFMA rows = gradient rows,
-// columns = outputs, K = (point, channel) pairs. A block of 8 waves owns 384
-// padded rows (3 row tiles per wave) and all outputs of one point slice; the
-// slice's bars (BF16, [j][point][channel]) and scaled jets are staged in
-// chunks, the next chunk's loads in flight meanwhile. A lane's gradient row
-// is fixed, so each K step it evaluates one basis row at the points of its
-// K group.
+// columns = outputs, K = (point, channel) pairs. A block of 8 waves owns 16
+// inputs (2 per wave) and all outputs of one point slice; the slice's bars
+// (BF16, [j][point][channel]) and scaled jets are staged in chunks,
+// the next chunk's loads in flight meanwhile. Row tile t of a wave holds
+// basis rows 8t .. 8t+7 of its two inputs (MFMA row m: input m / 8,
+// b = 8t + m % 8), so a lane's rows in every tile belong to one input: each
+// K step it reads that input's scaled jets once per point and evaluates its
+// NBP / 8 basis rows.
 // ---------------------------------------------------------------------------
 template <int O0, int O1, int S, int NQ, int NBP>
 struct DwDn {
@@ -546,13 +552,15 @@ struct DwDn {
     static constexpr int PC = KP > 16 ? KP : 16;           // points per staged chunk
     static constexpr int KSC = PC / KP;                    // K steps per chunk
     static constexpr int N = 16 * NQ;
-    static constexpr int MT = 3;                           // row tiles per wave
-    static constexpr int IB = DW_R / NBP;                  // inputs per block
+    static constexpr int MT = NBP / 8;                     // row tiles per wave
+    static constexpr int IB = 2 * (DW_T / 64);             // inputs per block
     static constexpr int YR = PC * CP + 8;                 // halfwords per staged bar row
-    static constexpr int NYP = S == 3 ? 2 : 1;
+    static constexpr int NYP = S == 3 ? 2 : 1;             // bar pieces
     static constexpr int YEL = N * YR;
     static constexpr int SJN = C == 1 ? 2 : 8;             // scaled-jet slots kept
-    static constexpr int JEL = PC * IB * SJN;
+    static constexpr int JPS = IB * SJN + 4;               // floats per staged point (padded: the lane
+                                                           // groups' points fall on distinct banks)
+    static constexpr int JEL = PC * JPS;
     static constexpr size_t lds() { return 2 * (size_t)NYP * YEL * sizeof(hw) + 2 * (size_t)JEL * sizeof(float); }
 };
 
@@ -568,12 +576,11 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
     constexpr int RY = (EY + DW_T - 1) / DW_T;
     constexpr int EJ = PC * IB;                // (point, input) pairs per chunk
     constexpr int RJ = (EJ + DW_T - 1) / DW_T;
-    static_assert(DW_R == (DW_T / 64) * MT * 16, "block rows");
     extern __shared__ __align__(16) float smem[];
     hw *sY = reinterpret_cast<hw *>(smem);                         // [2][NYP][N][YR]
-    float *sJ = smem + (2 * NYP * YEL) / 2;                        // [2][PC][IB][SJN]
+    float *sJ = smem + (2 * NYP * YEL) / 2;                        // [2][PC][JPS]
 
-    // XCD-aware order: the row blocks of one slice run on one XCD (blocks
+    // XCD-aware order: the input blocks of one slice run on one XCD (blocks
     // are dealt to the 8 XCDs round robin), so its bars come from one L2
     int kb, split;
     if (nsplit % 8 == 0) {
@@ -590,15 +597,11 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
     const int64_t per = ((n + nsplit - 1) / nsplit + PC - 1) / PC * PC;
     const int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
 
-    // this lane's gradient row in each tile: block-local input, offset cb
-    int jl[MT];
+    // this lane's input (block-local) and the offsets cb = 3/2 - b/2 of its rows
+    const int jl = 2 * wv + (r16 >> 3);
     float cb[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-        const int kk = wv * (MT * 16) + 16 * t + r16;
-        jl[t] = kk / NBP;
-        cb[t] = 1.5f - 0.5f * (float)(kk % NBP);
-    }
+    for (int t = 0; t < MT; ++t) cb[t] = 1.5f - 0.5f * (float)(8 * t + (r16 & 7));
 
     float ry[RY][C];
     float rj[RJ][C];
@@ -661,7 +664,7 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
             const int pp = e % PC, il = e / PC;
             float s[8];
             scale_jets<O0, O1>(rj[k], inv_w, zoff, s);
-            float *d = sJ + (size_t)buf * F::JEL + (pp * IB + il) * SJN;
+            float *d = sJ + (size_t)buf * F::JEL + pp * F::JPS + il * SJN;
             if constexpr (SJN == 2) {
                 *reinterpret_cast<f2v *>(d) = (f2v){s[0], s[1]};
             } else {
@@ -690,32 +693,35 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
 #pragma unroll 1
         for (int ks = 0; ks < KSC; ++ks) {
             const int pp0 = ks * KP + g * PG;      // first point of this lane's K group
-            bf8 ah[MT], al[MT];
+            float v[MT][8];
 #pragma unroll
-            for (int t = 0; t < MT; ++t) {
-                float v[8];
+            for (int e = 0; e < PG; ++e) {
+                const float *sp = J0 + (pp0 + e) * F::JPS + jl * SJN;
+                float s[8];
+                if constexpr (SJN == 2) {
+                    const f2v s0 = *reinterpret_cast<const f2v *>(sp);
+                    s[0] = s0[0];
+                    s[1] = s0[1];
+                } else {
+                    const f4 s0 = *reinterpret_cast<const f4 *>(sp), s1 = *reinterpret_cast<const f4 *>(sp + 4);
+                    s[0] = s0[0]; s[1] = s0[1]; s[2] = s0[2]; s[3] = s0[3];
+                    s[4] = s1[0]; s[5] = s1[1]; s[6] = s1[2]; s[7] = s1[3];
+                }
 #pragma unroll
-                for (int e = 0; e < PG; ++e) {
-                    const float *sp = J0 + ((pp0 + e) * IB + jl[t]) * SJN;
-                    float s[8];
-                    if constexpr (SJN == 2) {
-                        const f2v s0 = *reinterpret_cast<const f2v *>(sp);
-                        s[0] = s0[0];
-                        s[1] = s0[1];
-                    } else {
-                        const f4 s0 = *reinterpret_cast<const f4 *>(sp), s1 = *reinterpret_cast<const f4 *>(sp + 4);
-                        s[0] = s0[0]; s[1] = s0[1]; s[2] = s0[2]; s[3] = s0[3];
-                        s[4] = s1[0]; s[5] = s1[1]; s[6] = s1[2]; s[7] = s1[3];
-                    }
+                for (int t = 0; t < MT; ++t) {
                     float f[C];
                     dn_features<O0, O1>(s, cb[t], f);
 #pragma unroll
-                    for (int c = 0; c < CP; ++c) v[e * CP + c] = c < C ? f[c < C ? c : 0] : 0.f;
+                    for (int c = 0; c < CP; ++c) v[t][e * CP + c] = c < C ? f[c < C ? c : 0] : 0.f;
                 }
+            }
+            bf8 ah[MT], al[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
                 if constexpr (S >= 2)
-                    split8(v, ah[t], al[t]);
+                    split8(v[t], ah[t], al[t]);
                 else
-                    ah[t] = pack8(v);
+                    ah[t] = pack8(v[t]);
             }
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -723,12 +729,15 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
                 const bf8 bh = *reinterpret_cast<const bf8 *>(Y0 + o);
                 bf8 bl;
                 if constexpr (S == 3) bl = *reinterpret_cast<const bf8 *>(Y0 + YEL + o);
+                // consecutive products go to different accumulators
 #pragma unroll
-                for (int t = 0; t < MT; ++t) {
-                    acc[t][q] = mfma(ah[t], bh, acc[t][q]);
-                    if constexpr (S >= 2) acc[t][q] = mfma(al[t], bh, acc[t][q]);
-                    if constexpr (S == 3) acc[t][q] = mfma(ah[t], bl, acc[t][q]);
-                }
+                for (int t = 0; t < MT; ++t) acc[t][q] = mfma(ah[t], bh, acc[t][q]);
+                if constexpr (S >= 2)
+#pragma unroll
+                    for (int t = 0; t < MT; ++t) acc[t][q] = mfma(al[t], bh, acc[t][q]);
+                if constexpr (S == 3)
+#pragma unroll
+                    for (int t = 0; t < MT; ++t) acc[t][q] = mfma(ah[t], bl, acc[t][q]);
             }
         }
         if (pc + PC < pe) store(buf ^ 1);
@@ -736,19 +745,22 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
         buf ^= 1;
     }
 
+    // D row 4 g + r of tile t: input g / 2 of the wave, basis row 8 t + 4 (g % 2) + r
     const int64_t KN = (int64_t)win * nb * N;
+    const int i = i0 + 2 * wv + (g >> 1);
+    if (i < win) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t)
+        for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int kk = wv * (MT * 16) + 16 * t + 4 * g + r;
-            const int i = i0 + kk / NBP, b = kk % NBP;
-            if (i < win && b < nb) {
-                float *o = part + split * KN + (int64_t)(i * nb + b) * N + r16;
+            for (int r = 0; r < 4; ++r) {
+                const int b = 8 * t + 4 * (g & 1) + r;
+                if (b < nb) {
+                    float *o = part + split * KN + (int64_t)(i * nb + b) * N + r16;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) o[16 * q] = acc[t][q][r];
+                    for (int q = 0; q < NQ; ++q) o[16 * q] = acc[t][q][r];
+                }
             }
-        }
+    }
 }
 
 int nbp_of(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : nb <= 24 ? 24 : 0; }
@@ -795,6 +807,7 @@ static void set_lds_limit(const void *kf)
 #define DN_SWITCH(ch, S_, N_, nbp_, ...) \
     DN_CH_SWITCH(ch, DN_S_SWITCH(S_, DN_NQ_SWITCH(N_, DN_NBP_SWITCH(nbp_, __VA_ARGS__))))
 
+// copies of a layer: Wr, Wt, then (S = 3) Wt's and Wr's low pieces
 struct DnW {
     const hw *r, *t, *rl, *tl;
 };
@@ -804,8 +817,8 @@ DnW dn_w(const void *wdn, LayerShape ls, int S)
     const hw *b = static_cast<const hw *>(wdn);
     DnW w{b, b + e, nullptr, nullptr};
     if (S == 3) {
-        w.rl = b + 2 * e;
-        w.tl = b + 3 * e;
+        w.tl = b + 2 * e;
+        w.rl = b + 3 * e;
     }
     return w;
 }
@@ -840,7 +853,7 @@ bool dn_supported(LayerShape ls, bool first)
 size_t dn_w_bytes(LayerShape ls, int S)
 {
     const size_t e = (size_t)kpad_of(ls) * ls.wout;
-    return (S == 3 ? 4 : 2) * e * sizeof(hw);
+    return (size_t)(S == 3 ? 4 : 2) * e * sizeof(hw);
 }
 
 hipError_t launch_w_prep_dn(const float *W, void *wdn, LayerShape ls, int S, hipStream_t st)
@@ -849,8 +862,8 @@ hipError_t launch_w_prep_dn(const float *W, void *wdn, LayerShape ls, int S, hip
     const int64_t tot = (int64_t)kpad * ls.wout;
     hw *b = static_cast<hw *>(wdn);
     const size_t e = (size_t)tot;
-    k_w_prep<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(W, b, b + e, S == 3 ? b + 2 * e : nullptr,
-                                                          S == 3 ? b + 3 * e : nullptr, ls.win, ls.nb,
+    k_w_prep<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(W, b, b + e, S == 3 ? b + 3 * e : nullptr,
+                                                          S == 3 ? b + 2 * e : nullptr, ls.win, ls.nb,
                                                           nbp_of(ls.nb), ls.wout, kpad);
     return hipGetLastError();
 }
@@ -887,7 +900,7 @@ hipError_t launch_dx_dn(ChanCfg ch, const float *zin, const float *ybar, const v
     return hipGetLastError();
 }
 
-int dw_dn_row_blocks(LayerShape ls) { return (kpad_of(ls) + DW_R - 1) / DW_R; }
+int dw_dn_row_blocks(LayerShape ls) { return (ls.win + 2 * (DW_T / 64) - 1) / (2 * (DW_T / 64)); }
 
 int dw_dn_splits(int64_t n, LayerShape ls)
 {
