@@ -139,7 +139,9 @@ def main():
     ms = graph_ms if launch == "hip_graph" else eager_ms
     loss = step.loss.cpu().numpy()
 
-    # per-kernel times: HIP events around every launch, on its own stream
+    # per-kernel times: HIP events around every launch, in a pass of its own
+    # in which the library runs both point sets on one stream (each launch
+    # alone on the GPU)
     H.profile_enable(True)
     for _ in range(args.steps):
         step()

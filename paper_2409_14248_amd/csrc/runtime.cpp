@@ -707,12 +707,14 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         T *sv_int = (T *)(w + L.sv_int), *jets = (T *)(w + L.jets_int);
         T *sv_bc = (T *)(w + L.sv_bc), *ubc = (T *)(w + L.ubc);
         T *seed_int = (T *)(w + L.seed_int), *seed_bc = (T *)(w + L.seed_bc);
-        // boundary set on the side stream, interior set on the caller's
         char *wdn = w + L.wdn;
         if constexpr (std::is_same<T, float>::value)
             if (ni_ + nb_ > 0) TRY(prep_dense(ni, (const float *const *)W, wdn, stream));
+        // boundary set on a side stream, concurrent with the interior set;
+        // while per-launch profiling is on, both on the caller's stream, so
+        // that each launch's events time that launch alone
         Fork *fk = nullptr;
-        if (ni_ > 0 && nb_ > 0) TRY(get_fork(stream, &fk));
+        if (ni_ > 0 && nb_ > 0 && !prof_on()) TRY(get_fork(stream, &fk));
         if (fk) TRY(fork_to(fk, stream));
         if (nb_ > 0)
             TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
