@@ -272,12 +272,19 @@ __global__ __launch_bounds__(DN_T) void k_fwd_dn(const float *__restrict__ zin, 
                 else
                     ah[c] = pack8(A[c]);
             }
+            // weight operands one output tile ahead: a tile's read is in
+            // flight during the previous tile's products
+            auto ldw = [&](int q, bf8 &bh, bf8 &bl) {
+                const int o = (16 * q + r16) * RS + 32 * ks + 8 * g;
+                bh = *reinterpret_cast<const bf8 *>(W0 + o);
+                if constexpr (S == 3) bl = *reinterpret_cast<const bf8 *>(W0 + WEL + o);
+            };
+            bf8 nh, nl;
+            ldw(0, nh, nl);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int o = (16 * q + r16) * RS + 32 * ks + 8 * g;
-                const bf8 bh = *reinterpret_cast<const bf8 *>(W0 + o);
-                bf8 bl;
-                if constexpr (S == 3) bl = *reinterpret_cast<const bf8 *>(W0 + WEL + o);
+                const bf8 bh = nh, bl = nl;
+                if (q + 1 < NQ) ldw(q + 1, nh, nl);
                 // consecutive products go to different accumulators
 #pragma unroll
                 for (int c = 0; c < C; ++c) acc[c][q] = mfma(ah[c], bh, acc[c][q]);
@@ -723,12 +730,19 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
                 else
                     ah[t] = pack8(v[t]);
             }
+            // bar operands one output tile ahead: a tile's read is in flight
+            // during the previous tile's products
+            auto ldy = [&](int q, bf8 &bh, bf8 &bl) {
+                const int o = (16 * q + r16) * YR + pp0 * CP;
+                bh = *reinterpret_cast<const bf8 *>(Y0 + o);
+                if constexpr (S == 3) bl = *reinterpret_cast<const bf8 *>(Y0 + YEL + o);
+            };
+            bf8 nh, nl;
+            ldy(0, nh, nl);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int o = (16 * q + r16) * YR + pp0 * CP;
-                const bf8 bh = *reinterpret_cast<const bf8 *>(Y0 + o);
-                bf8 bl;
-                if constexpr (S == 3) bl = *reinterpret_cast<const bf8 *>(Y0 + YEL + o);
+                const bf8 bh = nh, bl = nl;
+                if (q + 1 < NQ) ldy(q + 1, nh, nl);
                 // consecutive products go to different accumulators
 #pragma unroll
                 for (int t = 0; t < MT; ++t) acc[t][q] = mfma(ah[t], bh, acc[t][q]);
