@@ -53,6 +53,20 @@ template <typename T>
 hipError_t launch_reduce_splits(const T *part, int nsplit, int64_t count, T *out, int accumulate,
                                 hipStream_t st);
 
+// The same for every layer of a network in one launch (blk0 is filled in by
+// the launcher).
+template <typename T>
+struct ReduceTable {
+    int L;
+    const T *part[HRKAN_MAX_LAYERS];
+    int nsplit[HRKAN_MAX_LAYERS];
+    int64_t count[HRKAN_MAX_LAYERS];
+    T *out[HRKAN_MAX_LAYERS];
+    int64_t blk0[HRKAN_MAX_LAYERS + 1];
+};
+template <typename T>
+hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t st);
+
 // Residual, seeds and per-block loss partials; then the final reduction.
 struct PdeParams {
     int kind;

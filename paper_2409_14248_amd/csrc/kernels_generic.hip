@@ -427,6 +427,55 @@ hipError_t launch_reduce_splits(const T *part, int nsplit, int64_t count, T *out
     return hipGetLastError();
 }
 
+// Every layer's reduction in one launch: blocks [blk0[l], blk0[l+1]) take
+// layer l, each element summed over its slices exactly as k_reduce_splits.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_reduce_layers(ReduceTable<T> tab, int accumulate)
+{
+    __shared__ double sh[RD_SL][RD_EB];
+    int l = 0;
+    while (l + 1 < tab.L && (int64_t)blockIdx.x >= tab.blk0[l + 1]) ++l;
+    const T *part = tab.part[l];
+    const int nsplit = tab.nsplit[l];
+    const int64_t count = tab.count[l];
+    T *out = tab.out[l];
+    const int el = threadIdx.x % RD_EB, sl = threadIdx.x / RD_EB;
+    const int64_t e = ((int64_t)blockIdx.x - tab.blk0[l]) * RD_EB + el;
+    double s = 0.0;
+    if (e < count) {
+        int k = sl;
+        for (; k + 7 * RD_SL < nsplit; k += 8 * RD_SL) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(k + u * RD_SL) * count + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += (double)v[u];
+        }
+        for (; k < nsplit; k += RD_SL) s += (double)part[(int64_t)k * count + e];
+    }
+    sh[sl][el] = s;
+    __syncthreads();
+    if (sl == 0 && e < count) {
+        double t = accumulate ? (double)out[e] : 0.0;
+        for (int k = 0; k < RD_SL; ++k) t += sh[k][el];
+        out[e] = (T)t;
+    }
+}
+
+template <typename T>
+hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t st)
+{
+    int64_t b = 0;
+    for (int l = 0; l < tab.L; ++l) {
+        tab.blk0[l] = b;
+        b += (tab.count[l] + RD_EB - 1) / RD_EB;
+    }
+    tab.blk0[tab.L] = b;
+    if (b == 0) return hipSuccess;
+    k_reduce_layers<T><<<(unsigned)b, NT, 0, st>>>(tab, accumulate);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // residual, seeds and per-block loss partials
 // ---------------------------------------------------------------------------
@@ -582,6 +631,7 @@ hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, in
     template hipError_t launch_dw_generic<T>(ChanCfg, bool, const T *, const T *, T *, int,      \
                                              int64_t, LayerShape, const GridP<T> &, hipStream_t); \
     template hipError_t launch_reduce_splits<T>(const T *, int, int64_t, T *, int, hipStream_t);  \
+    template hipError_t launch_reduce_layers<T>(ReduceTable<T>, int, hipStream_t);                 \
     template hipError_t launch_residual<T>(const PdeParams &, int, const T *, const T *, int64_t, \
                                            const T *, const T *, int64_t, T *, T *, T *,         \
                                            double *, int, hipStream_t);

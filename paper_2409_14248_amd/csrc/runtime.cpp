@@ -465,18 +465,22 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
     if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st, true, wdn));
     if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false, wdn));
     if (split) TRY(join_from(fk, st));
-    for (int l = ni.L - 1; l >= 0; --l) {
-        const int64_t kn = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
-        hipError_t e;
-        if (tot[l] == 0) {
-            if (accumulate) continue;
-            e = launch_reduce_splits<T>(part, 0, kn, gW[l], 0, st);   // writes zeros
-        } else {
-            ProfScope ps("reduce", l, st);
-            e = launch_reduce_splits<T>(part + base[l], tot[l], kn, gW[l], accumulate, st);
-        }
-        if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+    // every layer in one launch (a layer without slices gets zeros, or is
+    // left as it is when accumulating)
+    ReduceTable<T> tab{};
+    tab.L = ni.L;
+    for (int l = 0; l < ni.L; ++l) {
+        tab.part[l] = part + base[l];
+        tab.nsplit[l] = tot[l];
+        tab.count[l] = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+        tab.out[l] = gW[l];
     }
+    hipError_t e;
+    {
+        ProfScope ps("reduce", -1, st);
+        e = launch_reduce_layers<T>(tab, accumulate, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
     return HRKAN_OK;
 }
 
