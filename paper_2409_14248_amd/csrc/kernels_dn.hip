@@ -17,10 +17,14 @@
 // a_hi b_lo, where b is the weight (forward, input bars) or the output bar
 // (weight gradient).
 //
-// Bumps: with a = clamp(zt - b/2 + 3/2, 0, 2) the distance to the support
-// start, t = a (2 - a) is exactly zero off the support and every power of t
-// and of d = 2 - 2a stays bounded, so padding rows and far-away coordinates
-// give finite zeros; a NaN coordinate is carried by adding a NaN to t.
+// Bumps: with u = clamp(zt - b/2 + 1/2, -1, 1) the offset from the support
+// midpoint, t = 1 - u^2 (= a (2 - a) for a = u + 1 the distance to the
+// support start) is exactly zero off the support, d = 2 - 2a = -2u, and
+// 3 d^2 - 2 t = 14 u^2 - 2; every power stays bounded, so padding rows and
+// far-away coordinates give finite zeros; a NaN coordinate is carried by
+// adding a NaN to t. Near the support ends 1 - u^2 is the difference of
+// nearly equal values: its error there is a few FP32 units of 1, where the
+// bump value t^4 is below 1e-10.
 //
 // MFMA lane layout (16x16x32 BF16, wave of 64): lane l, r16 = l % 16,
 // g = l / 16:  A[r16][8g .. 8g+7],  B[8g .. 8g+7][r16],  D[4g + r][r16].
@@ -78,22 +82,23 @@ __device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Scaled jets of one (point, input): the scaled coordinate zt, the NaN
-// carrier, and the chain-rule factors of the features
-//   A_U = t^4,  A_X = kX td,  A_XX = kXX2 v2 + kXX1 td  (A_Y, A_YY alike),
-// td = t^3 d, v2 = t^2 (3 d^2 - 2 t); kX = 4w zx, kXX1 = 4w zxx,
-// kXX2 = 4w^2 zx^2 (w = inv_w), so that v' = 4w td and v'' = 4w^2 v2.
+// Scaled jets of one (point, input): the scaled coordinate zt, 1 plus the
+// NaN carrier, and the chain-rule factors of the features
+//   A_U = t^4,  A_X = kX tu,  A_XX = kXX2 v2 + kXX1 tu  (A_Y, A_YY alike),
+// tu = t^3 u, v2 = t^2 (u^2 - 1/7); kX = -8w zx, kXX1 = -8w zxx,
+// kXX2 = 56 w^2 zx^2 (w = inv_w), so that v' = 4w t^3 d = -8w tu and
+// v'' = 4w^2 t^2 (3 d^2 - 2 t) = 56 w^2 v2.
 enum { SZ = 0, SN = 1, SX = 2, SXX1 = 3, SXX2 = 4, SY = 5, SYY1 = 6, SYY2 = 7 };
 
 template <int O0, int O1>
 __device__ __forceinline__ void scale_jets(const float *zj, float inv_w, float zoff, float *s)
 {
     using CH = Ch<O0, O1>;
-    const float w1 = 4.f * inv_w, w2 = 4.f * inv_w * inv_w;
+    const float w1 = -8.f * inv_w, w2 = 56.f * inv_w * inv_w;
 #pragma unroll
     for (int k = 0; k < 8; ++k) s[k] = 0.f;
     s[SZ] = zj[CH::U] * inv_w + zoff;
-    s[SN] = __builtin_isnan(s[SZ]) ? s[SZ] : 0.f;
+    s[SN] = 1.f + (__builtin_isnan(s[SZ]) ? s[SZ] : 0.f);
     if constexpr (CH::X >= 0) s[SX] = w1 * zj[CH::X];
     if constexpr (CH::XX >= 0) {
         s[SXX1] = w1 * zj[CH::XX];
@@ -106,25 +111,24 @@ __device__ __forceinline__ void scale_jets(const float *zj, float inv_w, float z
     }
 }
 
-// Features of every channel for the basis row with offset cb = 3/2 - b/2.
+// Features of every channel for the basis row with offset cb = 1/2 - b/2.
 template <int O0, int O1>
 __device__ __forceinline__ void dn_features(const float *s, float cb, float *A)
 {
     using CH = Ch<O0, O1>;
-    const float a = fminf(fmaxf(s[SZ] + cb, 0.f), 2.f);
-    const float be = 2.f - a;
-    const float t = fmaf(a, be, s[SN]);
+    const float u = fminf(fmaxf(s[SZ] + cb, -1.f), 1.f);
+    const float u2 = u * u;
+    const float t = s[SN] - u2;
     const float t2 = t * t;
     A[CH::U] = t2 * t2;
     if constexpr (CH::X >= 0 || CH::Y >= 0) {
-        const float d = be - a;
-        const float td = t2 * t * d;
-        if constexpr (CH::X >= 0) A[CH::X] = s[SX] * td;
-        if constexpr (CH::Y >= 0) A[CH::Y] = s[SY] * td;
+        const float tu = t2 * t * u;
+        if constexpr (CH::X >= 0) A[CH::X] = s[SX] * tu;
+        if constexpr (CH::Y >= 0) A[CH::Y] = s[SY] * tu;
         if constexpr (CH::XX >= 0 || CH::YY >= 0) {
-            const float v2 = t2 * fmaf(3.f * d, d, -2.f * t);
-            if constexpr (CH::XX >= 0) A[CH::XX] = fmaf(s[SXX2], v2, s[SXX1] * td);
-            if constexpr (CH::YY >= 0) A[CH::YY] = fmaf(s[SYY2], v2, s[SYY1] * td);
+            const float v2 = t2 * (u2 - (1.f / 7.f));
+            if constexpr (CH::XX >= 0) A[CH::XX] = fmaf(s[SXX2], v2, s[SXX1] * tu);
+            if constexpr (CH::YY >= 0) A[CH::YY] = fmaf(s[SYY2], v2, s[SYY1] * tu);
         }
     }
 }
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(DN_T) void k_fwd_dn(const float *__restrict__ zin, 
             const float *sp = J0 + (il * DN_P + wv * 16 + r16) * 4;
             const f4 s0 = *reinterpret_cast<const f4 *>(sp), s1 = *reinterpret_cast<const f4 *>(sp + F::JEL / 2);
             const float s[8] = {s0[0], s0[1], s0[2], s0[3], s1[0], s1[1], s1[2], s1[3]};
-            const float cb0 = 1.5f - 0.5f * (float)b0;
+            const float cb0 = 0.5f - 0.5f * (float)b0;
             float A[C][8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(DN_T) void k_dx_dn(const float *__restrict__ zin, c
     const int64_t p = (int64_t)blockIdx.x * DN_P + wv * 16 + r16;   // this lane's point (D column)
     const bool pin = p < n;
     const int nch = (win + 1) / 2;
-    const float w1 = 4.f * inv_w, w2 = 4.f * inv_w * inv_w, w3 = 24.f * inv_w * inv_w * inv_w;
+    const float w1 = -8.f * inv_w, w2 = 56.f * inv_w * inv_w, w3 = -336.f * inv_w * inv_w * inv_w;
 
     // output bars of this lane's point, outputs 32 ks + 8 g + e, as B operands
     bf8 yh[C][KJ], yl[C][KJ];
@@ -457,29 +461,30 @@ __global__ __launch_bounds__(DN_T) void k_dx_dn(const float *__restrict__ zin, c
 #pragma unroll
             for (int c = 0; c < C; ++c) z[c] = h ? zj[1][c] : zj[0][c];
             const float zt = z[CH::U] * inv_w + zoff;
-            const float nz = __builtin_isnan(zt) ? zt : 0.f;
-            // scaled jet factors: P = sum of first-order bars times w2 z', Q
-            // = second-order bars times w3 z'^2
+            const float one = 1.f + (__builtin_isnan(zt) ? zt : 0.f);   // 1 plus the NaN carrier
+            // P = sum of first-order bars times z', Q = second-order bars
+            // times z'^2
             float zbt[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) zbt[c] = 0.f;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float a = fminf(fmaxf(zt + (1.5f - 0.5f * (float)(b0 + r)), 0.f), 2.f);
-                const float be = 2.f - a;
-                const float tt = fmaf(a, be, nz);
+                // u = offset from the support midpoint, t = 1 - u^2, d = -2u:
+                // v' = -8w t^3 u, v'' = 56 w^2 t^2 (u^2 - 1/7),
+                // v''' = -336 w^3 t u (u^2 - 3/7)
+                const float u = fminf(fmaxf(zt + (0.5f - 0.5f * (float)(b0 + r)), -1.f), 1.f);
+                const float u2 = u * u;
+                const float tt = one - u2;
                 const float t2 = tt * tt;
                 float Ab[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) Ab[c] = acc[c][r];
                 if constexpr (C == 1) {
-                    const float d = be - a;
-                    zbt[0] = fmaf(w1 * (t2 * tt * d), Ab[0], zbt[0]);
+                    zbt[0] = fmaf(w1 * (t2 * tt * u), Ab[0], zbt[0]);
                 } else {
-                    const float d = be - a;
-                    const float v1 = w1 * (t2 * tt * d);
-                    const float v2 = w2 * (t2 * fmaf(3.f * d, d, -2.f * tt));
-                    const float v3 = w3 * (tt * d * fmaf(-3.f, tt, d * d));
+                    const float v1 = w1 * (t2 * tt * u);
+                    const float v2 = w2 * (t2 * (u2 - (1.f / 7.f)));
+                    const float v3 = w3 * (tt * u * (u2 - (3.f / 7.f)));
                     float P = 0.f, Q = 0.f;
                     if constexpr (CH::X >= 0) {
                         P = fmaf(Ab[CH::X], z[CH::X], P);
@@ -604,11 +609,11 @@ __global__ __launch_bounds__(DW_T) void k_dw_dn(const float *__restrict__ zin, c
     const int64_t per = ((n + nsplit - 1) / nsplit + PC - 1) / PC * PC;
     const int64_t ps = (int64_t)split * per, pe = min(n, ps + per);
 
-    // this lane's input (block-local) and the offsets cb = 3/2 - b/2 of its rows
+    // this lane's input (block-local) and the offsets cb = 1/2 - b/2 of its rows
     const int jl = 2 * wv + (r16 >> 3);
     float cb[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) cb[t] = 1.5f - 0.5f * (float)(8 * t + (r16 & 7));
+    for (int t = 0; t < MT; ++t) cb[t] = 0.5f - 0.5f * (float)(8 * t + (r16 & 7));
 
     float ry[RY][C];
     float rj[RJ][C];

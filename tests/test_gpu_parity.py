@@ -238,27 +238,33 @@ def test_residual_call_matches_oracle():
     assert relerr(sb.cpu().numpy(), rsb) < 1e-13
 
 
-def test_autograd_functions_match_step():
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_autograd_functions_match_step(dtype):
+    """The two autograd Functions (separate forward-jets, residual and
+    backward calls) against the fused step: the same products, other
+    summation orders (BF16: the same BF16 pieces in both)."""
     pr = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=2000, n_bc=128)
-    nd = H.net_desc(pr.net, "f32")
+    nd = H.net_desc(pr.net, dtype)
     pd = H.pde_desc(pr.pde)
-    W = [to_dev(w, "f32").requires_grad_(True) for w in pr.W]
-    xi, xb, g = to_dev(pr.x_int, "f32"), to_dev(pr.x_bc, "f32"), to_dev(pr.g_bc, "f32")
+    W = [to_dev(w, dtype).requires_grad_(True) for w in pr.W]
+    xi, xb, g = to_dev(pr.x_int, dtype), to_dev(pr.x_bc, dtype), to_dev(pr.g_bc, dtype)
     jets = H.HRKANJets.apply(nd, H.MASK_BURGERS, xi, *W)
     ub = H.HRKANJets.apply(nd, H.MASK_VALUE, xb, *W)
     L, Lp, Lb = H.HRKANResidual.apply(pd, H.F32, jets, ub[0], xi, g)
     L.backward()
-    ref_loss, ref_gW, _ = gpu_step(pr, "f32")
+    ref_loss, ref_gW, _ = gpu_step(pr, dtype)
     assert abs(L.item() - ref_loss[0]) <= 1e-6 * abs(ref_loss[0])
     for w, b in zip(W, ref_gW):
         assert relerr(w.grad.double().cpu().numpy(), b) < 1e-5
 
 
-def test_graph_replay_matches_eager_step():
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_graph_replay_matches_eager_step(dtype):
     """The step captured in a HIP graph gives the eager result on every
-    replay, with eager work on the same buffers in between."""
+    replay, with eager work on the same buffers in between (BF16: including
+    the per-call BF16 weight copies of the dense kernels)."""
     pr = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=6000, n_bc=400)
-    st = H.Step(pr, "f32")
+    st = H.Step(pr, dtype)
     loss0, gW0 = st()
     torch.cuda.synchronize()
     ref_loss = loss0.cpu().numpy().copy()
