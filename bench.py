@@ -32,6 +32,7 @@ PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2409_14248_amd", "csrc", "kernels_bs32.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_burgers_c2_f32.md")
+TRAFFIC_RUN = ("burgers_c2", "f32")     # the workload and dtype those counters were taken on
 
 
 def parse():
@@ -78,9 +79,12 @@ def kernel_flops(pr, C, live=False):
     return out
 
 
-def traffic_record(kernel_name, launches_per_step):
+def traffic_record(kernel_name, launches_per_step, workload, dtype):
     """HBM bytes per launch of a kernel from the committed counter summary,
-    if that summary was taken on the current kernel source; else None."""
+    if that summary was taken on this workload and the current kernel
+    source; else None."""
+    if (workload, dtype) != TRAFFIC_RUN:
+        return None
     if not os.path.exists(TRAFFIC_FILE) or not os.path.exists(KERNEL_SRC):
         return None
     txt = open(TRAFFIC_FILE).read()
@@ -171,7 +175,7 @@ def main():
     roofline = {
         "bound": "mfma", "kernel": dname, "achieved": round(achieved, 3), "peak": peak,
         "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-        "traffic": traffic_record(dname, launches_per_step),
+        "traffic": traffic_record(dname, launches_per_step, args.workload, dtype),
         "flops_per_launch": f_dense, "launch_ms": round(per_launch_ms, 5),
         "achieved_live": round(achieved_live, 3), "frac_live": round(achieved_live / peak, 4),
         "live_flops_per_launch": f_live, "kernel_share": round(dms / args.steps / total_ms, 3),
