@@ -198,6 +198,22 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
                const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
                size_t ws_bytes, hipStream_t stream);
 
+/* Adam update of every layer's weights in place, for training with the
+ * optimiser the paper uses (Sec. 4.1, 4.2: Adam, 3000 epochs), with the
+ * published update of Kingma and Ba: with t = *step_dev + 1,
+ *   m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *   W -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * elementwise over W[l], gW[l], m[l], v[l] (host arrays of n_layers device
+ * pointers, each [w_l * n_b, w_{l+1}], array type of the net: FP64 for
+ * HRKAN_F64, else FP32; m and v zero before the first update). step_dev is
+ * a device int64 (zero before the first update) that the call advances by
+ * one after the update, so a step and its update captured together in a
+ * HIP graph replay with the right bias corrections. Requires lr >= 0,
+ * 0 <= beta1, beta2 < 1, eps > 0; asynchronous on `stream`. */
+int hrkan_adam(const hrkan_net_desc *net, void *const *W, const void *const *gW, void *const *m,
+               void *const *v, int64_t *step_dev, double lr, double beta1, double beta2, double eps,
+               hipStream_t stream);
+
 /* ---------------------------------------------------------------------- */
 /* Batched step: many independent instances of one network shape, each with */
 /* its own weights, PDE coefficients and point counts, run by one           */

@@ -273,3 +273,21 @@ def step(net, pde, Ws, x_int, x_bc, g_bc):
                           nbc, _ptr(g_bc), _ptr(loss), garr, _ptr(r), _ptr(jets), _ptr(ubc))
     assert rc == 0
     return {"loss": loss, "gW": gWs, "r": r, "jets": jets, "u_bc": ubc}
+
+
+def adam(Ws, gWs, ms, vs, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """The Adam optimiser the paper trains with (Sec. 4.1, 4.2), in the
+    update of Kingma and Ba: step t (1, 2, ...) with gradients gWs; returns
+    new (Ws, ms, vs) as float64 arrays, one element at a time in plain
+    numpy arithmetic."""
+    out_w, out_m, out_v = [], [], []
+    for w, g, m, v in zip(Ws, gWs, ms, vs):
+        w, g, m, v = (np.asarray(a, dtype=np.float64) for a in (w, g, m, v))
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        mhat = m / (1.0 - beta1 ** t)
+        vhat = v / (1.0 - beta2 ** t)
+        out_w.append(w - lr * mhat / (np.sqrt(vhat) + eps))
+        out_m.append(m)
+        out_v.append(v)
+    return out_w, out_m, out_v

@@ -67,6 +67,22 @@ struct ReduceTable {
 template <typename T>
 hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t st);
 
+// Adam update of every layer in one launch, then the device step count
+// advanced (blk0 filled in by the launcher).
+template <typename T>
+struct AdamTable {
+    int L;
+    T *W[HRKAN_MAX_LAYERS];
+    const T *g[HRKAN_MAX_LAYERS];
+    T *m[HRKAN_MAX_LAYERS];
+    T *v[HRKAN_MAX_LAYERS];
+    int64_t count[HRKAN_MAX_LAYERS];
+    int64_t blk0[HRKAN_MAX_LAYERS + 1];
+};
+template <typename T>
+hipError_t launch_adam(AdamTable<T> tab, int64_t *tdev, double lr, double b1, double b2, double eps,
+                       hipStream_t st);
+
 // Residual, seeds and per-block loss partials; then the final reduction.
 struct PdeParams {
     int kind;

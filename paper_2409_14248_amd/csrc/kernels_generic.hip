@@ -462,6 +462,46 @@ __global__ __launch_bounds__(NT) void k_reduce_layers(ReduceTable<T> tab, int ac
     }
 }
 
+// Adam update of every layer's weights (one launch): with t = *tdev + 1,
+//   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+//   W -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
+// blocks [blk0[l], blk0[l+1]) take layer l. The step count lives in device
+// memory (k_adam_count advances it), so a captured step replays correctly.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adam(AdamTable<T> tab, const int64_t *__restrict__ tdev, double lr,
+                                             double b1, double b2, double eps)
+{
+    int l = 0;
+    while (l + 1 < tab.L && (int64_t)blockIdx.x >= tab.blk0[l + 1]) ++l;
+    const int64_t e = ((int64_t)blockIdx.x - tab.blk0[l]) * NT + threadIdx.x;
+    if (e >= tab.count[l]) return;
+    const double t = (double)(*tdev + 1);
+    const double c1 = 1.0 / (1.0 - pow(b1, t)), c2 = 1.0 / (1.0 - pow(b2, t));
+    const T g = tab.g[l][e];
+    const T m = (T)b1 * tab.m[l][e] + (T)(1.0 - b1) * g;
+    const T v = (T)b2 * tab.v[l][e] + (T)(1.0 - b2) * g * g;
+    tab.m[l][e] = m;
+    tab.v[l][e] = v;
+    tab.W[l][e] -= (T)lr * (m * (T)c1) / (sqrt(v * (T)c2) + (T)eps);
+}
+
+__global__ void k_adam_count(int64_t *tdev) { tdev[0] += 1; }
+
+template <typename T>
+hipError_t launch_adam(AdamTable<T> tab, int64_t *tdev, double lr, double b1, double b2, double eps,
+                       hipStream_t st)
+{
+    int64_t b = 0;
+    for (int l = 0; l < tab.L; ++l) {
+        tab.blk0[l] = b;
+        b += (tab.count[l] + NT - 1) / NT;
+    }
+    tab.blk0[tab.L] = b;
+    if (b > 0) k_adam<T><<<(unsigned)b, NT, 0, st>>>(tab, tdev, lr, b1, b2, eps);
+    k_adam_count<<<1, 1, 0, st>>>(tdev);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t st)
 {
@@ -632,6 +672,7 @@ hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, in
                                              int64_t, LayerShape, const GridP<T> &, hipStream_t); \
     template hipError_t launch_reduce_splits<T>(const T *, int, int64_t, T *, int, hipStream_t);  \
     template hipError_t launch_reduce_layers<T>(ReduceTable<T>, int, hipStream_t);                 \
+    template hipError_t launch_adam<T>(AdamTable<T>, int64_t *, double, double, double, double, hipStream_t); \
     template hipError_t launch_residual<T>(const PdeParams &, int, const T *, const T *, int64_t, \
                                            const T *, const T *, int64_t, T *, T *, T *,         \
                                            double *, int, hipStream_t);

@@ -753,6 +753,41 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
     return run(float{});
 }
 
+int hrkan_adam(const hrkan_net_desc *net, void *const *W, const void *const *gW, void *const *m,
+               void *const *v, int64_t *step_dev, double lr, double beta1, double beta2, double eps,
+               hipStream_t stream)
+{
+    NetInfo ni;
+    TRY(check_net(net, &ni));
+    TRY(check_weights(ni, (const void *const *)W, "W"));
+    TRY(check_weights(ni, gW, "gW"));
+    TRY(check_weights(ni, (const void *const *)m, "m"));
+    TRY(check_weights(ni, (const void *const *)v, "v"));
+    if (!step_dev) return fail(HRKAN_ERR_INVALID_ARG, "step_dev is NULL");
+    if (!aligned(step_dev, 8)) return fail(HRKAN_ERR_INVALID_ARG, "step_dev misaligned");
+    if (!(lr >= 0.0) || !std::isfinite(lr)) return fail(HRKAN_ERR_INVALID_ARG, "lr must be finite and >= 0");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return fail(HRKAN_ERR_INVALID_ARG, "betas must lie in [0, 1)");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(HRKAN_ERR_INVALID_ARG, "eps must be finite and > 0");
+    hipError_t e;
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        AdamTable<T> tab{};
+        tab.L = ni.L;
+        for (int l = 0; l < ni.L; ++l) {
+            tab.W[l] = (T *)W[l];
+            tab.g[l] = (const T *)gW[l];
+            tab.m[l] = (T *)m[l];
+            tab.v[l] = (T *)v[l];
+            tab.count[l] = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+        }
+        return launch_adam<T>(tab, step_dev, lr, beta1, beta2, eps, stream);
+    };
+    e = ni.dtype == HRKAN_F64 ? run(double{}) : run(float{});
+    if (e != hipSuccess) return hip_fail(e, "adam launch");
+    return HRKAN_OK;
+}
+
 int hrkan_read_status(void *ws, size_t ws_bytes, hipStream_t stream, uint32_t *flags)
 {
     if (!flags) return fail(HRKAN_ERR_INVALID_ARG, "flags is NULL");

@@ -38,7 +38,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_PLAN_MISMAT
 EXPORTS = [
     "hrkan_net_init", "hrkan_pde_init", "hrkan_mask_channels", "hrkan_saved_bytes",
     "hrkan_workspace_bytes", "hrkan_forward_jets", "hrkan_residual", "hrkan_backward",
-    "hrkan_step", "hrkan_plan_workspace_bytes", "hrkan_plan_create", "hrkan_plan_execute",
+    "hrkan_step", "hrkan_adam", "hrkan_plan_workspace_bytes", "hrkan_plan_create", "hrkan_plan_execute",
     "hrkan_plan_config", "hrkan_plan_destroy", "hrkan_read_status", "hrkan_status_string",
     "hrkan_last_error", "hrkan_version", "hrkan_profile_enable", "hrkan_profile_read",
 ]
@@ -108,6 +108,8 @@ def lib():
     L.hrkan_residual.argtypes = [P(PdeDesc), i32, vp, vp, P(Points), vp, vp, vp, vp, vp, sz, vp]
     L.hrkan_backward.argtypes = [P(NetDesc), P(vp), vp, i64, u32, vp, vp, P(vp), i32, vp, sz, vp]
     L.hrkan_step.argtypes = [P(NetDesc), P(PdeDesc), P(vp), P(Points), vp, P(vp), vp, sz, vp]
+    L.hrkan_adam.argtypes = [P(NetDesc), P(vp), P(vp), P(vp), P(vp), vp, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, vp]
     L.hrkan_plan_workspace_bytes.argtypes = [P(NetDesc), i32, P(Points), P(sz)]
     L.hrkan_plan_create.argtypes = [P(vp), P(NetDesc), i32, P(PdeDesc), vp, P(Points), vp, vp, vp,
                                     sz, vp]
@@ -281,6 +283,16 @@ def step(nd: NetDesc, pd: PdeDesc, W: Sequence[torch.Tensor], x_int: torch.Tenso
     return loss_out, gW_out
 
 
+def adam(nd: NetDesc, W: Sequence[torch.Tensor], gW: Sequence[torch.Tensor], m: Sequence[torch.Tensor],
+         v: Sequence[torch.Tensor], step_dev: torch.Tensor, lr: float, betas=(0.9, 0.999), eps: float = 1e-8,
+         stream=None) -> None:
+    """Adam update of W in place (m, v: moment buffers; step_dev: device int64
+    step count, advanced by the call)."""
+    check(lib().hrkan_adam(ctypes.byref(nd), _ptr_array(W), _ptr_array(gW), _ptr_array(m), _ptr_array(v),
+                           _ptr(step_dev), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                           _stream(stream)))
+
+
 def profile_enable(on: bool = True) -> None:
     check(lib().hrkan_profile_enable(int(bool(on))))
 
@@ -342,6 +354,58 @@ class Step:
     def replay(self):
         self.graph.replay()
         return self.loss, self.gW
+
+
+class Trainer:
+    """Step plus Adam on resident buffers: run(epochs) trains the network on
+    its collocation points; each epoch is one hrkan_step and one hrkan_adam,
+    replayed from one HIP graph when graph=True."""
+
+    def __init__(self, problem: _wl.Problem, dtype="f32", lr: float = 1e-2, betas=(0.9, 0.999),
+                 eps: float = 1e-8, bf16_split: int = 2, device="cuda"):
+        self.step = Step(problem, dtype, bf16_split, device)
+        self.m = [torch.zeros_like(w) for w in self.step.W]
+        self.v = [torch.zeros_like(w) for w in self.step.W]
+        self.t = torch.zeros(1, dtype=torch.int64, device=device)
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.graph = None
+
+    def epoch(self):
+        loss, gW = self.step()
+        adam(self.step.nd, self.step.W, gW, self.m, self.v, self.t, self.lr, self.betas, self.eps)
+        return loss
+
+    def capture(self):
+        """Record one epoch (step and update) into a HIP graph; the weights,
+        moments and step count it updates live in device memory."""
+        saved = [w.clone() for w in self.step.W] + [a.clone() for a in self.m + self.v] + [self.t.clone()]
+        self.epoch()                              # eager first run: one-time kernel setup
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.epoch()
+        torch.cuda.synchronize()
+        # undo the warm-up epoch
+        n = len(self.step.W)
+        for dst, src in zip(self.step.W + self.m + self.v + [self.t], saved):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        return self.graph
+
+    def run(self, epochs: int, graph: bool = True, record_every: int = 0):
+        """Train for `epochs` epochs; returns the loss history {epoch: [L, L_pde, L_bc]}
+        sampled every record_every epochs (and at the last)."""
+        if graph and self.graph is None:
+            self.capture()
+        hist = {}
+        for e in range(epochs):
+            if graph:
+                self.graph.replay()
+            else:
+                self.epoch()
+            if (record_every and e % record_every == 0) or e == epochs - 1:
+                hist[e] = self.step.loss.cpu().tolist()
+        return hist
 
 
 # ---------------------------------------------------------------------------

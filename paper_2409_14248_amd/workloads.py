@@ -1,6 +1,6 @@
 """Seeded synthetic inputs for the HRKAN training step (numpy only).
 
-This module holds no arithmetic of the method: it only describes the five
+This module holds no arithmetic of the method: it only describes the
 workloads (network shape, PDE instance, point counts, precision) and draws the
 collocation points, boundary/initial targets and N(0, 0.1^2) weights from a
 seeded generator. Both the GPU binding's users and the CPU oracle's users take
@@ -97,6 +97,7 @@ class Workload:
     seed: int
     grid_points: bool = False   # c1: tensor grid instead of random interior
     n_instances: int = 1
+    recipe: str = ""            # "burgers_paper": the paper's own Burgers points and targets
 
 
 def _cell_centred(lo: float, hi: float, n: int) -> np.ndarray:
@@ -149,6 +150,25 @@ def burgers_points(n_int: int, n_bc: int, rng: np.random.Generator):
     return x_int, x_bc, g
 
 
+def burgers_paper_points(n_int: int, n_bc: int, rng: np.random.Generator):
+    """The paper's Burgers instance after its change of variable (Sec. 4.2):
+    interior of [0,2.5]^2; a third of the extra points on the initial line
+    t = 0 with target 1/cosh(4x - 5), a third on each wall x = 0, x = 2.5
+    with target 0."""
+    x = rng.uniform(0.0, 2.5, size=n_int)
+    t = rng.uniform(0.0, 2.5, size=n_int)
+    x_int = np.stack([x, t], axis=1)
+    k = n_bc // 3
+    assert 3 * k == n_bc
+    xi = _cell_centred(0.0, 2.5, k)
+    tw = _cell_centred(0.0, 2.5, k)
+    x_bc = np.concatenate([
+        np.stack([xi, np.zeros(k)], 1),
+        np.stack([np.zeros(k), tw], 1), np.stack([np.full(k, 2.5), tw], 1)], axis=0)
+    g = np.concatenate([1.0 / np.cosh(4.0 * xi - 5.0), np.zeros(2 * k)])
+    return x_int, x_bc, g
+
+
 NU_BURGERS = 0.01 / math.pi
 
 WORKLOADS = {
@@ -168,6 +188,16 @@ WORKLOADS = {
     "burgers_batched_c5": Workload("burgers_batched_c5", Net((2, 32, 32, 1), G=10),
                                    Pde(BURGERS1D, NU_BURGERS), 0, 0, "f32", SEED_BASE + 4,
                                    n_instances=256),
+    # the paper's Poisson training run (Sec. 4.1): [2,2,1], g=5, 960 random
+    # interior points, 30 evenly spaced points per edge, FP32
+    "poisson_paper": Workload("poisson_paper", Net((2, 2, 1), G=5), Pde(POISSON2D),
+                              960, 120, "f32", SEED_BASE + 5),
+    # the paper's Burgers instance (Sec. 4.2) on [0,2.5]^2: u_t + u u_x / 4 -
+    # nu / 16 u_xx with nu = 0.001, [2,3,3,3,1], g=7 on the same range,
+    # 10,000 + 100 initial + 2 x 100 wall points, FP32
+    "burgers_paper": Workload("burgers_paper", Net((2, 3, 3, 3, 1), G=7, lo=0.0, hi=2.5),
+                              Pde(BURGERS1D, 0.001 / 16.0, adv=0.25), 10000, 300, "f32",
+                              SEED_BASE + 6, recipe="burgers_paper"),
 }
 
 
@@ -183,6 +213,8 @@ def make_problem(wl: Workload, n_int: Optional[int] = None, n_bc: Optional[int] 
     pde = wl.pde if pde is None else pde
     if pde.kind == POISSON2D:
         x_int, x_bc, g = poisson_points(n_int, n_bc, rx, grid=wl.grid_points and n_int == wl.n_int)
+    elif wl.recipe == "burgers_paper":
+        x_int, x_bc, g = burgers_paper_points(n_int, n_bc, rx)
     else:
         x_int, x_bc, g = burgers_points(n_int, n_bc, rx)
     return Problem(wl.net, pde, W, x_int, x_bc, g)

@@ -234,3 +234,26 @@ def test_plan_calls_reject_null_plan():
     assert L.hrkan_plan_execute(None, None) == H.ERR_PLAN_MISMATCH
     assert L.hrkan_plan_config(None, None, None) == H.ERR_PLAN_MISMATCH
     L.hrkan_plan_destroy(None)
+
+
+def test_adam_argument_errors():
+    """hrkan_adam validates its pointers and hyper-parameters on the host."""
+    net = WL.Net((2, 32, 32, 1), G=10)
+    nd = H.net_desc(net, "f32")
+    L = len(net.weight_shapes())
+    fake = (ctypes.c_void_p * L)(*([0x10000] * L))      # aligned, never dereferenced
+    null = (ctypes.c_void_p * L)(*([0] * L))
+    t = ctypes.c_void_p(0x10000)
+
+    def call(W=fake, g=fake, m=fake, v=fake, tdev=t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        return H.lib().hrkan_adam(ctypes.byref(nd), W, g, m, v, tdev, lr, b1, b2, eps, None)
+
+    assert call(W=null) == H.ERR_INVALID_ARG
+    assert call(v=null) == H.ERR_INVALID_ARG
+    assert call(tdev=ctypes.c_void_p(0)) == H.ERR_INVALID_ARG
+    assert call(tdev=ctypes.c_void_p(0x10004)) == H.ERR_INVALID_ARG     # misaligned counter
+    assert call(lr=-1.0) == H.ERR_INVALID_ARG
+    assert call(lr=float("nan")) == H.ERR_INVALID_ARG
+    assert call(b1=1.0) == H.ERR_INVALID_ARG
+    assert call(b2=-0.1) == H.ERR_INVALID_ARG
+    assert call(eps=0.0) == H.ERR_INVALID_ARG
