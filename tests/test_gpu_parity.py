@@ -80,6 +80,33 @@ def test_step_f64_at_each_network_shape(name):
         assert relerr(a, b) < 1e-10
 
 
+@pytest.mark.parametrize("k,m", [(3, 2), (3, 3), (3, 5), (2, 4), (1, 3), (0, 2)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_step_other_orders(k, m, dtype):
+    """Other support widths k and HR orders m (Eq. 2; m = 2 is the
+    ReLU-KAN basis of Eq. 1) run on the generic kernels; the FP64 step meets
+    1e-10 against the oracle, the FP32 step its rounding-model gate. With
+    m = 2 the second derivative of a bump jumps at its support ends (the
+    smoothness argument of Sec. 2.3); random points fall on no knot, so the
+    comparison stays well defined."""
+    net = WL.Net((2, 6, 5, 1), G=6, k=k, m=m)
+    wl = WL.Workload("orders", net, WL.Pde(WL.BURGERS1D, WL.NU_BURGERS), 700, 48, dtype,
+                     WL.SEED_BASE + 40 + 7 * k + m)
+    pr = WL.make_problem(wl)
+    loss, gW, ws = gpu_step(pr, dtype)
+    assert H.read_status(ws) == 0
+    if dtype == "f64":
+        ref = oracle_step(pr, "f64")
+        assert relerr(loss, ref["loss"]) < 1e-10
+        for a, b in zip(gW, ref["gW"]):
+            assert relerr(a, b) < 1e-10
+    else:
+        ref, gl, gg = fp32_step_gates(pr)
+        assert relerr(loss, ref["loss"]) < gl
+        for a, b, gt in zip(gW, ref["gW"], gg):
+            assert relerr(a, b) < gt
+
+
 # ---------------------------------------------------------------------------
 # FP32 path
 # ---------------------------------------------------------------------------
