@@ -233,7 +233,8 @@ int get_fork(hipStream_t st, Fork **out)
     if ((e = hipStreamCreateWithFlags(&en.f.side, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "side stream");
     if ((e = hipEventCreateWithFlags(&en.f.fork, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&en.f.join, hipEventDisableTiming)) != hipSuccess)
+        (e = hipEventCreateWithFlags(&en.f.join, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&en.f.mid, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "fork events");
     ++ntab;
     *out = &en.f;
@@ -394,7 +395,7 @@ struct RevSet {
 
 template <typename T>
 int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const int64_t *off, T *part,
-                hipStream_t st, bool bc, const char *wdn)
+                hipStream_t st, bool bc, const char *wdn, hipEvent_t mark = nullptr, int mark_layer = -1)
 {
     const GridP<T> g = make_grid<T>(ni);
     const T *ybar = S.seed;
@@ -418,6 +419,8 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             }
         }
         if (e != hipSuccess) return hip_fail(e, "weight-gradient launch");
+        if (mark && l == mark_layer && (e = hipEventRecord(mark, st)) != hipSuccess)
+            return hip_fail(e, "event record");
         if (l == 0) break;
         T *zbar = (ybar == S.bar0) ? S.bar1 : S.bar0;
         {
@@ -441,8 +444,11 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
 
 // Reverse pass of up to two point sets sharing W. Layer l's partial region
 // holds all slices of set 0, then all of set 1; with a fork the second set
-// runs on the side stream. The regions are reduced into gW at the end, each
-// element summed over its slices in that fixed order.
+// runs on the side stream. Each gradient element is summed over its slices in
+// that fixed order. With a fork, layers 1.. are reduced on the side stream as
+// soon as both sets have written them (concurrent with the first set's last
+// input bars and layer-0 slices); layer 0, or every layer without a fork, at
+// the end on the caller's stream.
 template <typename T>
 int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, int nsets,
                  T *const *gW, int accumulate, T *part, hipStream_t st, Fork *fk, const char *wdn)
@@ -461,27 +467,35 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
         o += part_layer_elems(ni, l, n0, n1);
     }
     const bool split = fk && n0 > 0 && n1 > 0;
+    const bool early = split && ni.L >= 2;
+    // a layer without slices gets zeros, or is left as it is when accumulating
+    auto reduce = [&](int l0, int l1, hipStream_t rs) -> int {
+        ReduceTable<T> tab{};
+        tab.L = l1 - l0;
+        for (int l = l0; l < l1; ++l) {
+            tab.part[l - l0] = part + base[l];
+            tab.nsplit[l - l0] = tot[l];
+            tab.count[l - l0] = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+            tab.out[l - l0] = gW[l];
+        }
+        hipError_t e;
+        {
+            ProfScope ps("reduce", -1, rs);
+            e = launch_reduce_layers<T>(tab, accumulate, rs);
+        }
+        return e == hipSuccess ? HRKAN_OK : hip_fail(e, "gradient reduction launch");
+    };
     if (split) TRY(fork_to(fk, st));
     if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st, true, wdn));
-    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false, wdn));
+    if (n0 > 0)
+        TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false, wdn, early ? fk->mid : nullptr, 1));
+    if (early) {
+        const hipError_t e = hipStreamWaitEvent(fk->side, fk->mid, 0);
+        if (e != hipSuccess) return hip_fail(e, "stream wait");
+        TRY(reduce(1, ni.L, fk->side));
+    }
     if (split) TRY(join_from(fk, st));
-    // every layer in one launch (a layer without slices gets zeros, or is
-    // left as it is when accumulating)
-    ReduceTable<T> tab{};
-    tab.L = ni.L;
-    for (int l = 0; l < ni.L; ++l) {
-        tab.part[l] = part + base[l];
-        tab.nsplit[l] = tot[l];
-        tab.count[l] = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
-        tab.out[l] = gW[l];
-    }
-    hipError_t e;
-    {
-        ProfScope ps("reduce", -1, st);
-        e = launch_reduce_layers<T>(tab, accumulate, st);
-    }
-    if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
-    return HRKAN_OK;
+    return reduce(0, early ? 1 : ni.L, st);
 }
 
 int check_ws(void *ws, size_t ws_bytes, size_t need)
@@ -679,6 +693,10 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
                                (float *)(w + L.part), stream, nullptr, w + L.wdn);
 }
 
+// Interior points times the widest hidden layer up to which the step runs
+// the two point sets concurrently (65,536 x 32 overlaps; 262,144 x 64 does not).
+constexpr int64_t OVERLAP_MAX_WORK = (int64_t)4 << 20;
+
 int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
                const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
                size_t ws_bytes, hipStream_t stream)
@@ -714,11 +732,19 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         char *wdn = w + L.wdn;
         if constexpr (std::is_same<T, float>::value)
             if (ni_ + nb_ > 0) TRY(prep_dense(ni, (const float *const *)W, wdn, stream));
-        // boundary set on a side stream, concurrent with the interior set;
-        // while per-launch profiling is on, both on the caller's stream, so
-        // that each launch's events time that launch alone
+        // Boundary set on a side stream, concurrent with the interior set,
+        // when the interior's launches are short: overlapping them hides
+        // launch gaps. The hidden-layer launches of a larger set fill the GPU
+        // in one round of blocks, and any kernel beside them pushes some of
+        // those blocks into a second round, which costs more than the
+        // overlap gains; there both sets run on the caller's stream, as they
+        // do while per-launch profiling is on (each launch's events then
+        // time that launch alone).
+        int wmax = 0;
+        for (int l = 1; l < ni.L; ++l) wmax = std::max(wmax, ni.w[l]);
+        const bool overlap = ni_ > 0 && nb_ > 0 && !prof_on() && ni_ * (int64_t)wmax <= OVERLAP_MAX_WORK;
         Fork *fk = nullptr;
-        if (ni_ > 0 && nb_ > 0 && !prof_on()) TRY(get_fork(stream, &fk));
+        if (overlap) TRY(get_fork(stream, &fk));
         if (fk) TRY(fork_to(fk, stream));
         if (nb_ > 0)
             TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
@@ -736,10 +762,13 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
                                    L.nres, stream);
         }
         if (e != hipSuccess) return hip_fail(e, "residual launch");
+        // no gradient needs the loss value: with a fork its final sum runs on
+        // the side stream, beside the interior set's reverse pass
+        if (fk) TRY(fork_to(fk, stream));
         {
-            ProfScope ps("loss", -1, stream);
-            e = launch_loss_final(partials, L.nres, ni_, nb_, pde->alpha, loss_out, (uint32_t *)w,
-                                  stream);
+            hipStream_t ls = fk ? fk->side : stream;
+            ProfScope ps("loss", -1, ls);
+            e = launch_loss_final(partials, L.nres, ni_, nb_, pde->alpha, loss_out, (uint32_t *)w, ls);
         }
         if (e != hipSuccess) return hip_fail(e, "loss launch");
         RevSet<T> sets[2] = {

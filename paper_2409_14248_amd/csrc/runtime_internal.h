@@ -46,7 +46,7 @@ int64_t part_layer_elems(const NetInfo &ni, int l, int64_t n_a, int64_t n_b);
 // Side stream and events of one caller stream (see get_fork).
 struct Fork {
     hipStream_t side;
-    hipEvent_t fork, join;
+    hipEvent_t fork, join, mid;   // mid: the caller's stream part-way through a pass
 };
 int get_fork(hipStream_t st, Fork **out);
 int fork_to(Fork *f, hipStream_t st);      // side waits for st's work so far
