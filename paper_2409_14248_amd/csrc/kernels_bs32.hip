@@ -934,8 +934,41 @@ static size_t dw_bs_lds(int C, int nb, int N, int II)
 
 // ---------------------------------------------------------------------------
 // last layer (one output): plain vector-ALU kernels
+//
+// They work with sums over the 4 window rows b = qa + r of one (point, input)
+// in the support-midpoint form: u_r = clamp(zt + 1/2 - b/2, -1, 1) and
+// t_r = 1 - u_r^2 (= a (2 - a) with a = u_r + 1; exactly zero off the
+// support, so no row needs a select), d = -2 u_r, and with weights w_r
+//   P0 = sum w t^4,  P1 = sum w t^3 u,  P2 = sum w t^2 (u^2 - 1/7),
+//   P3 = sum w t u (u^2 - 3/7),
+// the weighted sums of the bump and its derivatives are
+//   sum w v = P0,  sum w dv = -8 iw P1,  sum w d2v = 56 iw^2 P2,
+//   sum w d3v = -336 iw^3 P3   (iw = inv_w, dv = v', d2v = v'', d3v = v'''),
+// so the chain rule of the jets is applied once per (point, input), not per
+// row. A NaN coordinate is carried by adding it to t (sn = 1 + NaN).
 // ---------------------------------------------------------------------------
-// u_c[p] = sum_i sum_t W[i*nb + qa + t] * A_c(p, i, t); 4 threads per point
+template <int NP>
+__device__ __forceinline__ void window_sums(float zt, float sn, int qa, const float *w4, float *P)
+{
+    const float c0 = zt + 0.5f - 0.5f * (float)qa;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) P[k] = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float u = fminf(fmaxf(c0 - 0.5f * (float)r, -1.f), 1.f);
+        const float u2 = u * u;
+        const float t = sn - u2;
+        const float t2 = t * t;
+        P[0] = fmaf(w4[r], t2 * t2, P[0]);
+        if constexpr (NP >= 2) P[1] = fmaf(w4[r], t2 * t * u, P[1]);
+        if constexpr (NP >= 3) P[2] = fmaf(w4[r], t2 * (u2 - (1.f / 7.f)), P[2]);
+        if constexpr (NP >= 4) P[3] = fmaf(w4[r], t * u * (u2 - (3.f / 7.f)), P[3]);
+    }
+}
+
+__device__ __forceinline__ float nan_carrier(float zt) { return 1.f + (__builtin_isnan(zt) ? zt : 0.f); }
+
+// u_c[p] = sum_i sum_r W[i*nb + qa + r] * A_c(p, i, r); 4 threads per point
 // (consecutive lanes), each taking every 4th input with all its loads in
 // flight, the 4 partial sums added across the quad.
 constexpr int FL_U = 8;   // inputs per thread whose loads are in flight together
@@ -945,10 +978,13 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
                                                  float *__restrict__ out, int64_t n, int win,
                                                  GridP<float> g, BatchMap bm)
 {
-    constexpr int C = Ch<O0, O1>::C;
+    using CH = Ch<O0, O1>;
+    constexpr int C = CH::C;
+    constexpr int NP = C > 1 ? 3 : 1;
     extern __shared__ float sW[];
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
+    const float k1 = -8.f * inv_w, k2 = 56.f * inv_w * inv_w;
     const float *Wb = W;
     if (bm.tile_inst) Wb += (int64_t)bm.tile_inst[((int64_t)blockIdx.x * (NT / 4)) >> 7] * bm.w_stride;
     for (int e = threadIdx.x; e < win * nb; e += NT) sW[e] = Wb[e];
@@ -972,16 +1008,21 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
         for (int u = 0; u < FL_U; ++u) {
             const int i = i0 + 4 * u;
             if (i >= win) break;
-            const float zt = zj[u][0] * inv_w + zoff;
+            const float zt = zj[u][CH::U] * inv_w + zoff;
             const int qa = window_k3(zt, nb);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                float v[3], A[C];
-                bump_k3m4<2>(zt, qa + t, inv_w, v);
-                features<float, O0, O1>(v, zj[u], A);
-                const float w = sW[i * nb + qa + t];
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[c] += w * A[c];
+            const float *wr = sW + i * nb + qa;
+            const float w4[4] = {wr[0], wr[1], wr[2], wr[3]};
+            float P[NP];
+            window_sums<NP>(zt, nan_carrier(zt), qa, w4, P);
+            acc[CH::U] += P[0];
+            if constexpr (C > 1) {
+                const float s1 = k1 * P[1], s2 = k2 * P[2];
+                if constexpr (CH::X >= 0) acc[CH::X] = fmaf(zj[u][CH::X], s1, acc[CH::X]);
+                if constexpr (CH::XX >= 0)
+                    acc[CH::XX] += fmaf(zj[u][CH::X] * zj[u][CH::X], s2, zj[u][CH::XX] * s1);
+                if constexpr (CH::Y >= 0) acc[CH::Y] = fmaf(zj[u][CH::Y], s1, acc[CH::Y]);
+                if constexpr (CH::YY >= 0)
+                    acc[CH::YY] += fmaf(zj[u][CH::Y] * zj[u][CH::Y], s2, zj[u][CH::YY] * s1);
             }
         }
     }
@@ -993,7 +1034,10 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
     }
 }
 
-// zbar[c][i][p] from ubar[c][p]; one thread per (point, input)
+// zbar[c][i][p] from ubar[c][p]; one thread per (point, input). With
+// S1..S3 the weighted sums of dv, d2v, d3v (the feature bars are w_r ubar_c):
+//   zbar_U  = ubar_U S1 + sum_d [ubar_d S2 zd + ubar_dd (S3 zd^2 + S2 zdd)]
+//   zbar_d  = ubar_d S1 + 2 ubar_dd S2 zd,   zbar_dd = ubar_dd S1
 template <int O0, int O1>
 __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
                                                 const float *__restrict__ ybar,
@@ -1001,7 +1045,9 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
                                                 float *__restrict__ zbar, int64_t n, int win,
                                                 GridP<float> g, BatchMap bm)
 {
-    constexpr int C = Ch<O0, O1>::C;
+    using CH = Ch<O0, O1>;
+    constexpr int C = CH::C;
+    constexpr int NP = C > 1 ? 4 : 2;
     const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (e >= n * win) return;
     const int i = (int)(e / n);
@@ -1014,25 +1060,47 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
     for (int c = 0; c < C; ++c) {
         zj[c] = zin[((int64_t)c * win + i) * n + p];
         yb[c] = ybar[(int64_t)c * n + p];
-        zb[c] = 0.f;
     }
-    const float zt = zj[0] * inv_w + zoff;
+    const float zt = zj[CH::U] * inv_w + zoff;
     const int qa = window_k3(zt, nb);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        float v[4], Ab[C];
-        bump_k3m4<3>(zt, qa + t, inv_w, v);
-        const float w = W[i * nb + qa + t];
-#pragma unroll
-        for (int c = 0; c < C; ++c) Ab[c] = w * yb[c];
-        features_adjoint<float, O0, O1>(v, zj, Ab, zb);
+    const float *wr = W + i * nb + qa;
+    const float w4[4] = {wr[0], wr[1], wr[2], wr[3]};
+    float P[NP];
+    window_sums<NP>(zt, nan_carrier(zt), qa, w4, P);
+    const float S1 = (-8.f * inv_w) * P[1];
+    float z0 = yb[CH::U] * S1;
+    if constexpr (C > 1) {
+        const float S2 = (56.f * inv_w * inv_w) * P[2];
+        const float S3 = (-336.f * inv_w * inv_w * inv_w) * P[3];
+        if constexpr (CH::X >= 0) {
+            z0 = fmaf(yb[CH::X] * zj[CH::X], S2, z0);
+            zb[CH::X] = yb[CH::X] * S1;
+        }
+        if constexpr (CH::XX >= 0) {
+            z0 = fmaf(yb[CH::XX], fmaf(zj[CH::X] * zj[CH::X], S3, zj[CH::XX] * S2), z0);
+            zb[CH::X] = fmaf(2.f * yb[CH::XX] * zj[CH::X], S2, zb[CH::X]);
+            zb[CH::XX] = yb[CH::XX] * S1;
+        }
+        if constexpr (CH::Y >= 0) {
+            z0 = fmaf(yb[CH::Y] * zj[CH::Y], S2, z0);
+            zb[CH::Y] = yb[CH::Y] * S1;
+        }
+        if constexpr (CH::YY >= 0) {
+            z0 = fmaf(yb[CH::YY], fmaf(zj[CH::Y] * zj[CH::Y], S3, zj[CH::YY] * S2), z0);
+            zb[CH::Y] = fmaf(2.f * yb[CH::YY] * zj[CH::Y], S2, zb[CH::Y]);
+            zb[CH::YY] = yb[CH::YY] * S1;
+        }
     }
+    zb[CH::U] = z0;
 #pragma unroll
     for (int c = 0; c < C; ++c) zbar[((int64_t)c * win + i) * n + p] = zb[c];
 }
 
 // gW[i*nb + b] for one point slice; thread (i, lane-slot) owns a private
-// accumulator row in LDS, so every sum has a fixed order.
+// accumulator row in LDS, so every sum has a fixed order. Row r of a
+// (point, input) adds sum_c A_c ubar_c = t^4 ubar_U + t^3 u G1 + t^2 (u^2 -
+// 1/7) G2 with G1 = -8 iw sum_d (zd ubar_d + zdd ubar_dd) and
+// G2 = 56 iw^2 sum_d zd^2 ubar_dd.
 constexpr int DL_SL = 8;   // point lanes per input
 template <int O0, int O1>
 __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
@@ -1040,11 +1108,13 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
                                                 float *__restrict__ part, int64_t n, int win,
                                                 int nsplit, GridP<float> g, BatchMap bm)
 {
-    constexpr int C = Ch<O0, O1>::C;
+    using CH = Ch<O0, O1>;
+    constexpr int C = CH::C;
     constexpr int IB = NT / DL_SL;        // inputs per block
     __shared__ float sacc[NT][33];
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
+    const float k1 = -8.f * inv_w, k2 = 56.f * inv_w * inv_w;
     const int li = threadIdx.x / DL_SL, sl = threadIdx.x % DL_SL;
     const int i = blockIdx.x * IB + li;
     const int split = blockIdx.y;
@@ -1072,17 +1142,35 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (p0 + (int64_t)u * DL_SL >= pe) break;
-                const float zt = zj[u][0] * inv_w + zoff;
+                const float zt = zj[u][CH::U] * inv_w + zoff;
+                const float sn = nan_carrier(zt);
                 const int qa = window_k3(zt, nb);
+                float G1 = 0.f, G2 = 0.f;
+                if constexpr (CH::X >= 0) G1 = fmaf(zj[u][CH::X], yb[u][CH::X], G1);
+                if constexpr (CH::XX >= 0) {
+                    G1 = fmaf(zj[u][CH::XX], yb[u][CH::XX], G1);
+                    G2 = fmaf(zj[u][CH::X] * zj[u][CH::X], yb[u][CH::XX], G2);
+                }
+                if constexpr (CH::Y >= 0) G1 = fmaf(zj[u][CH::Y], yb[u][CH::Y], G1);
+                if constexpr (CH::YY >= 0) {
+                    G1 = fmaf(zj[u][CH::YY], yb[u][CH::YY], G1);
+                    G2 = fmaf(zj[u][CH::Y] * zj[u][CH::Y], yb[u][CH::YY], G2);
+                }
+                G1 *= k1;
+                G2 *= k2;
+                const float c0 = zt + 0.5f - 0.5f * (float)qa;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    float v[3], A[C];
-                    bump_k3m4<2>(zt, qa + t, inv_w, v);
-                    features<float, O0, O1>(v, zj[u], A);
-                    float sum = 0.f;
-#pragma unroll
-                    for (int c = 0; c < C; ++c) sum += A[c] * yb[u][c];
-                    sacc[threadIdx.x][qa + t] += sum;
+                for (int r = 0; r < 4; ++r) {
+                    const float uu = fminf(fmaxf(c0 - 0.5f * (float)r, -1.f), 1.f);
+                    const float u2 = uu * uu;
+                    const float t = sn - u2;
+                    const float t2 = t * t;
+                    float sum = t2 * t2 * yb[u][CH::U];
+                    if constexpr (C > 1) {
+                        sum = fmaf(t2 * t * uu, G1, sum);
+                        sum = fmaf(t2 * (u2 - (1.f / 7.f)), G2, sum);
+                    }
+                    sacc[threadIdx.x][qa + r] += sum;
                 }
             }
         }
