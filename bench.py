@@ -30,7 +30,8 @@ METRIC = "PINN train-step collocation points/s (fwd jets+residual+bwd), bf16 vs 
 # MI355X published dense peaks (TFLOP/s) and HBM bandwidth (GB/s)
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2409_14248_amd", "csrc", "kernels_bs32.hip")
+# the kernels and the launch sequence the counter summary was taken on
+KERNEL_SRC = [os.path.join(ROOT, "paper_2409_14248_amd", "csrc", f) for f in ("kernels_bs32.hip", "runtime.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_burgers_c2_f32.md")
 TRAFFIC_RUN = ("burgers_c2", "f32")     # the workload and dtype those counters were taken on
 
@@ -38,8 +39,8 @@ TRAFFIC_RUN = ("burgers_c2", "f32")     # the workload and dtype those counters 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="burgers_c2")
     ap.add_argument("--dtype", default=None, help="f64 | f32 | bf16 (default: the workload's)")
     ap.add_argument("--bf16-split", type=int, default=2)
@@ -70,12 +71,17 @@ def layer_flops(net, C, n, live=False):
     return out
 
 
-def kernel_flops(pr, C, live=False):
-    """Flops of every profiled launch name (interior names, and _bc names for
-    the boundary set with one channel)."""
+def kernel_flops(pr, C, live=False, merged=False):
+    """Algorithmic flops of every profiled launch name: the interior set with
+    C channels under the interior names and the boundary set with one channel
+    under the _bc names; when the step runs the boundary points as more rows
+    of the interior set (merged), the interior names carry both."""
     out = dict(layer_flops(pr.net, C, pr.n_int, live))
     for k, v in layer_flops(pr.net, 1, pr.n_bc, live).items():
-        out[k + "_bc"] = v
+        if merged:
+            out[k] += v
+        else:
+            out[k + "_bc"] = v
     return out
 
 
@@ -85,11 +91,11 @@ def traffic_record(kernel_name, launches_per_step, workload, dtype):
     source; else None."""
     if (workload, dtype) != TRAFFIC_RUN:
         return None
-    if not os.path.exists(TRAFFIC_FILE) or not os.path.exists(KERNEL_SRC):
+    if not os.path.exists(TRAFFIC_FILE) or not all(os.path.exists(f) for f in KERNEL_SRC):
         return None
     txt = open(TRAFFIC_FILE).read()
     m = re.search(r"kernel source sha256:\s*([0-9a-f]{64})", txt)
-    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    cur = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()
     if not m or m.group(1) != cur:
         return None
     m = re.search(r"^\|\s*%s\s*\|\s*([0-9.eE+]+)\s*\|" % re.escape(kernel_name), txt, re.M)
@@ -128,8 +134,8 @@ def main():
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / k
 
-    # the step launched from the host (its boundary set runs concurrently on a
-    # side stream) and replayed from a HIP graph; the faster is reported
+    # the step launched from the host and replayed from a HIP graph; the
+    # faster is reported
     for _ in range(args.warmup):
         step()
     eager_ms = timed(step, args.steps)
@@ -144,10 +150,9 @@ def main():
     loss = step.loss.cpu().numpy()
 
     # per-kernel times: HIP events around every launch, in a pass of its own
-    # in which the library runs both point sets on one stream (each launch
-    # alone on the GPU)
+    prof_steps = min(args.steps, 50)
     H.profile_enable(True)
-    for _ in range(args.steps):
+    for _ in range(prof_steps):
         step()
     torch.cuda.synchronize()
     prof = H.profile_read()
@@ -160,13 +165,14 @@ def main():
         torch.cuda.synchronize()
 
     C = H.mask_channels(H.pde_mask(pr.pde.kind))
-    dense = kernel_flops(pr, C)
-    live = kernel_flops(pr, C, live=True)
-    total_ms = sum(v[1] for v in prof.values()) / args.steps
+    merged = pr.n_bc > 0 and "fwd_l0_bc" not in prof
+    dense = kernel_flops(pr, C, merged=merged)
+    live = kernel_flops(pr, C, live=True, merged=merged)
+    total_ms = sum(v[1] for v in prof.values()) / prof_steps
     contraction = {k: v for k, v in prof.items() if k in dense}
     dname, (dcnt, dms) = max(contraction.items(), key=lambda kv: kv[1][1])
     per_launch_ms = dms / dcnt
-    launches_per_step = dcnt / args.steps
+    launches_per_step = dcnt / prof_steps
     f_dense = dense[dname] / launches_per_step
     f_live = live[dname] / launches_per_step
     peak = PEAK[dtype]
@@ -178,7 +184,7 @@ def main():
         "traffic": traffic_record(dname, launches_per_step, args.workload, dtype),
         "flops_per_launch": f_dense, "launch_ms": round(per_launch_ms, 5),
         "achieved_live": round(achieved_live, 3), "frac_live": round(achieved_live / peak, 4),
-        "live_flops_per_launch": f_live, "kernel_share": round(dms / args.steps / total_ms, 3),
+        "live_flops_per_launch": f_live, "kernel_share": round(dms / prof_steps / total_ms, 3),
     }
     step_flops = sum(dense.values())
 
@@ -227,7 +233,7 @@ def main():
         "loss": [float(v) for v in loss],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels_ms_per_step": {k: round(v[1] / args.steps, 5) for k, v in sorted(prof.items())},
+        "kernels_ms_per_step": {k: round(v[1] / prof_steps, 5) for k, v in sorted(prof.items())},
     }
     print(json.dumps(out))
 

@@ -63,6 +63,12 @@ struct ReduceTable {
     int64_t count[HRKAN_MAX_LAYERS];
     T *out[HRKAN_MAX_LAYERS];
     int64_t blk0[HRKAN_MAX_LAYERS + 1];
+    // optional: one more block sums the loss partials as k_loss_final does
+    const double *loss_part;     // [loss_nblk][2], or null
+    int loss_nblk;
+    double inv_int, inv_bc, alpha;
+    double *loss_out;
+    uint32_t *status;
 };
 template <typename T>
 hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t st);
@@ -92,7 +98,18 @@ template <typename T>
 hipError_t launch_residual(const PdeParams &pde, int C, const T *jets, const T *x_int,
                            int64_t n_int, const T *u_bc, const T *g_bc, int64_t n_bc, T *r_out,
                            T *seed_int, T *seed_bc, double *partials, int nblk, hipStream_t st);
-int residual_blocks(int64_t n_int, int64_t n_bc);
+// The interior and boundary sets as one set (training steps of small sets):
+// points concatenated, and the residual with the boundary misfit on the value
+// channel of rows n_int.. of [C][n_int + n_bc] jets and seeds.
+template <typename T>
+hipError_t launch_concat_points(const T *x_int, int64_t n_int, const T *x_bc, int64_t n_bc, T *out,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_residual_merged(const PdeParams &pde, int C, const T *jets, const T *x_int, int64_t n_int,
+                                  const T *g_bc, int64_t n_bc, T *seed, double *partials, int nblk,
+                                  hipStream_t st);
+int residual_blocks(int64_t n_int, int64_t n_bc);   // partial slots for both sets
+int residual_blocks_of(int64_t n);                  // blocks of one set's residual launch
 hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, int64_t n_bc,
                              double alpha, double *loss_out, uint32_t *status, hipStream_t st);
 

@@ -385,6 +385,50 @@ hipError_t launch_dw_generic(ChanCfg ch, bool first, const T *zin, const T *ybar
 // each sum a fixed residue class of slices in double, then one thread adds
 // the 8 lane sums in order: a fixed summation order for every element.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of v over the block (256 threads = 4 waves), fixed order; valid in
+// thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// Loss from the per-block partials (interior squared residuals, boundary
+// squared misfits), one block of NT threads: L = alpha L_pde + L_bc.
+__device__ __forceinline__ void loss_block(const double *__restrict__ partials, int nblk, double inv_int,
+                                           double inv_bc, double alpha, double *__restrict__ loss_out,
+                                           uint32_t *__restrict__ status, double *sh)
+{
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += NT) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
+    }
+    const double sa = block_sum(a, sh);
+    const double sb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        const double lpde = sa * inv_int, lbc = sb * inv_bc;
+        const double L = alpha * lpde + lbc;
+        loss_out[0] = L;
+        loss_out[1] = lpde;
+        loss_out[2] = lbc;
+        if (!isfinite(L)) status[0] |= HRKAN_STATUS_NONFINITE;
+    }
+}
+
 constexpr int RD_EB = 32, RD_SL = NT / RD_EB;
 
 template <typename T>
@@ -433,6 +477,11 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_reduce_layers(ReduceTable<T> tab, int accumulate)
 {
     __shared__ double sh[RD_SL][RD_EB];
+    if (tab.loss_part && (int64_t)blockIdx.x == tab.blk0[tab.L]) {
+        loss_block(tab.loss_part, tab.loss_nblk, tab.inv_int, tab.inv_bc, tab.alpha, tab.loss_out,
+                   tab.status, &sh[0][0]);
+        return;
+    }
     int l = 0;
     while (l + 1 < tab.L && (int64_t)blockIdx.x >= tab.blk0[l + 1]) ++l;
     const T *part = tab.part[l];
@@ -511,6 +560,7 @@ hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t 
         b += (tab.count[l] + RD_EB - 1) / RD_EB;
     }
     tab.blk0[tab.L] = b;
+    if (tab.loss_part) ++b;
     if (b == 0) return hipSuccess;
     k_reduce_layers<T><<<(unsigned)b, NT, 0, st>>>(tab, accumulate);
     return hipGetLastError();
@@ -519,27 +569,6 @@ hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t 
 // ---------------------------------------------------------------------------
 // residual, seeds and per-block loss partials
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Sum of v over the block (256 threads = 4 waves), fixed order; valid in
-// thread 0.
-__device__ __forceinline__ double block_sum(double v, double *sh)
-{
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) sh[wv] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    __syncthreads();
-    return r;
-}
-
 template <typename T> __device__ __forceinline__ T sin_pi(T v);
 template <> __device__ __forceinline__ double sin_pi<double>(double v) { return sinpi(v); }
 template <> __device__ __forceinline__ float sin_pi<float>(float v) { return sinpif(v); }
@@ -606,9 +635,11 @@ __global__ __launch_bounds__(NT) void k_residual(const T *__restrict__ jets,
 
 int residual_blocks(int64_t n_int, int64_t n_bc)
 {
-    const int64_t b = (n_int + n_bc + NT - 1) / NT;
+    // room for the two sets in launches of their own
+    const int64_t b = (n_int + NT - 1) / NT + (n_bc + NT - 1) / NT;
     return (int)(b < 1 ? 1 : b);
 }
+int residual_blocks_of(int64_t n) { return (int)((n + NT - 1) / NT); }
 
 template <typename T>
 hipError_t launch_residual(const PdeParams &pde, int C, const T *jets, const T *x_int,
@@ -637,21 +668,100 @@ __global__ __launch_bounds__(NT) void k_loss_final(const double *__restrict__ pa
                                                    uint32_t *__restrict__ status)
 {
     __shared__ double sh[4];
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += NT) {
-        a += partials[2 * i];
-        b += partials[2 * i + 1];
+    loss_block(partials, nblk, inv_int, inv_bc, alpha, loss_out, status, sh);
+}
+
+// One point set of both: the interior points, then the boundary points
+// (interleaved coordinate pairs).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_concat_points(const T *__restrict__ x_int, int64_t n_int,
+                                                      const T *__restrict__ x_bc, int64_t n_bc,
+                                                      T *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e < 2 * n_int)
+        out[e] = x_int[e];
+    else if (e < 2 * (n_int + n_bc))
+        out[e] = x_bc[e - 2 * n_int];
+}
+
+template <typename T>
+hipError_t launch_concat_points(const T *x_int, int64_t n_int, const T *x_bc, int64_t n_bc, T *out,
+                                hipStream_t st)
+{
+    const int64_t m = 2 * (n_int + n_bc);
+    if (m == 0) return hipSuccess;
+    k_concat_points<T><<<(unsigned)((m + NT - 1) / NT), NT, 0, st>>>(x_int, n_int, x_bc, n_bc, out);
+    return hipGetLastError();
+}
+
+// Residual, misfit and seeds of the merged set: jets and seeds are
+// [C][n_int + n_bc]; points p < n_int are interior (as k_residual), the rest
+// boundary points, whose seed is the misfit's on the value channel and zero
+// on the others (their derivative channels carry no loss term).
+template <typename T, int KIND>
+__global__ __launch_bounds__(NT) void k_residual_merged(const T *__restrict__ jets,
+                                                        const T *__restrict__ x_int, int64_t n_int,
+                                                        const T *__restrict__ g_bc, int64_t n_bc, int C,
+                                                        T *__restrict__ seed,
+                                                        double *__restrict__ partials, T nu, T adv,
+                                                        T sc_int, T sc_bc)
+{
+    __shared__ double sh[4];
+    const int64_t ns = n_int + n_bc;
+    const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
+    double e_pde = 0.0, e_bc = 0.0;
+    if (p < n_int) {
+        T r;
+        if constexpr (KIND == 0) {
+            const T uxx = jets[2 * ns + p], uyy = jets[4 * ns + p];
+            const T x = x_int[2 * p], y = x_int[2 * p + 1];
+            const T f = T(2.0 * 9.869604401089358) * sin_pi(x) * sin_pi(y);
+            r = uxx + uyy + f;
+            const T rho = sc_int * r;
+            seed[0 * ns + p] = T(0);
+            seed[1 * ns + p] = T(0);
+            seed[2 * ns + p] = rho;
+            seed[3 * ns + p] = T(0);
+            seed[4 * ns + p] = rho;
+        } else {
+            const T u = jets[p], ux = jets[ns + p], uxx = jets[2 * ns + p], ut = jets[3 * ns + p];
+            r = ut + adv * u * ux - nu * uxx;
+            const T rho = sc_int * r;
+            seed[0 * ns + p] = rho * adv * ux;
+            seed[1 * ns + p] = rho * adv * u;
+            seed[2 * ns + p] = -rho * nu;
+            seed[3 * ns + p] = rho;
+        }
+        e_pde = (double)r * (double)r;
+    } else if (p < ns) {
+        const T d = jets[p] - g_bc[p - n_int];
+        seed[p] = sc_bc * d;
+        for (int c = 1; c < C; ++c) seed[c * ns + p] = T(0);
+        e_bc = (double)d * (double)d;
     }
-    const double sa = block_sum(a, sh);
-    const double sb = block_sum(b, sh);
+    const double s0 = block_sum(e_pde, sh);
+    const double s1 = block_sum(e_bc, sh);
     if (threadIdx.x == 0) {
-        const double lpde = sa * inv_int, lbc = sb * inv_bc;
-        const double L = alpha * lpde + lbc;
-        loss_out[0] = L;
-        loss_out[1] = lpde;
-        loss_out[2] = lbc;
-        if (!isfinite(L)) status[0] |= HRKAN_STATUS_NONFINITE;
+        partials[2 * blockIdx.x] = s0;
+        partials[2 * blockIdx.x + 1] = s1;
     }
+}
+
+template <typename T>
+hipError_t launch_residual_merged(const PdeParams &pde, int C, const T *jets, const T *x_int, int64_t n_int,
+                                  const T *g_bc, int64_t n_bc, T *seed, double *partials, int nblk,
+                                  hipStream_t st)
+{
+    const T sc_int = n_int > 0 ? (T)(2.0 * pde.alpha / (double)n_int) : T(0);
+    const T sc_bc = n_bc > 0 ? (T)(2.0 / (double)n_bc) : T(0);
+    if (pde.kind == 0)
+        k_residual_merged<T, 0><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials,
+                                                     (T)pde.nu, (T)pde.adv, sc_int, sc_bc);
+    else
+        k_residual_merged<T, 1><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials,
+                                                     (T)pde.nu, (T)pde.adv, sc_int, sc_bc);
+    return hipGetLastError();
 }
 
 hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, int64_t n_bc,
@@ -675,7 +785,10 @@ hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, in
     template hipError_t launch_adam<T>(AdamTable<T>, int64_t *, double, double, double, double, hipStream_t); \
     template hipError_t launch_residual<T>(const PdeParams &, int, const T *, const T *, int64_t, \
                                            const T *, const T *, int64_t, T *, T *, T *,         \
-                                           double *, int, hipStream_t);
+                                           double *, int, hipStream_t);                          \
+    template hipError_t launch_concat_points<T>(const T *, int64_t, const T *, int64_t, T *, hipStream_t); \
+    template hipError_t launch_residual_merged<T>(const PdeParams &, int, const T *, const T *, int64_t, \
+                                                  const T *, int64_t, T *, double *, int, hipStream_t);
 HRK_INST(float)
 HRK_INST(double)
 

@@ -200,10 +200,41 @@ int cu_blocks()
     return cached;
 }
 
-// A second stream per (device, caller stream): the boundary point set runs
-// on it concurrently with the interior set, joined by events. Streams and
-// events are created on first use and kept for the life of the process;
-// the stream has the default priority.
+// How a training step runs its interior and boundary sets, by the interior
+// points times the widest hidden layer (measured on the FP32 kernels):
+//  - up to MERGE_MAX_WORK (the paper's instances, 1,024 x 8): as one set, the
+//    boundary points as more rows of the interior set with the interior's jet
+//    channels (their derivative channels get zero seeds, so they add no term
+//    to the loss or the gradient). The boundary set's own launches would cost
+//    more than its points do there.
+//  - up to OVERLAP_MAX_WORK (65,536 x 32): the boundary set on a side stream,
+//    beside the interior set, which hides launch gaps.
+//  - above it (262,144 x 64) one after the other on the caller's stream: a
+//    hidden-layer launch of such a set fills the GPU in one round of blocks,
+//    and a kernel beside it pushes some of those blocks into a second round,
+//    which costs more than the overlap gains.
+constexpr int64_t MERGE_MAX_WORK = (int64_t)1 << 20;
+constexpr int64_t OVERLAP_MAX_WORK = (int64_t)4 << 20;
+
+static int64_t set_work(const NetInfo &ni, int64_t n_int)
+{
+    int wmax = 0;
+    for (int l = 1; l < ni.L; ++l) wmax = std::max(wmax, ni.w[l]);
+    return n_int * (int64_t)wmax;
+}
+
+bool merged_sets(const NetInfo &ni, int64_t n_int, int64_t n_bc)
+{
+    return n_int > 0 && n_bc > 0 && set_work(ni, n_int) <= MERGE_MAX_WORK;
+}
+
+static bool overlap_sets(const NetInfo &ni, int64_t n_int, int64_t n_bc)
+{
+    return n_int > 0 && n_bc > 0 && !merged_sets(ni, n_int, n_bc) && set_work(ni, n_int) <= OVERLAP_MAX_WORK;
+}
+
+// A second stream per (device, caller stream), for overlap_sets: created on
+// first use and kept for the life of the process, at the default priority.
 int get_fork(hipStream_t st, Fork **out)
 {
     struct Entry {
@@ -224,7 +255,7 @@ int get_fork(hipStream_t st, Fork **out)
             return HRKAN_OK;
         }
     if (ntab == 64) {
-        *out = nullptr;   // table full: the caller runs both sets on st
+        *out = nullptr;
         return HRKAN_OK;
     }
     Entry &en = tab[ntab];
@@ -233,8 +264,7 @@ int get_fork(hipStream_t st, Fork **out)
     if ((e = hipStreamCreateWithFlags(&en.f.side, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "side stream");
     if ((e = hipEventCreateWithFlags(&en.f.fork, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&en.f.join, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&en.f.mid, hipEventDisableTiming)) != hipSuccess)
+        (e = hipEventCreateWithFlags(&en.f.join, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "fork events");
     ++ntab;
     *out = &en.f;
@@ -272,28 +302,32 @@ static int64_t part_elems_total(const NetInfo &ni, int64_t n_a, int64_t n_b)
 }
 
 // Workspace regions, in bytes from the start of ws. Sizes use 5 channels for
-// interior sets so one layout serves both PDE kinds.
+// interior sets so one layout serves both PDE kinds. A merged step keeps its
+// one set in the interior regions.
 WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
 {
     WsLayout L{};
     const size_t E = ni.elem;
-    const int64_t nmax = std::max<int64_t>(std::max(n_int, n_bc), 1);
+    L.merged = merged_sets(ni, n_int, n_bc);
+    const int64_t na = L.merged ? n_int + n_bc : n_int, nbs = L.merged ? 0 : n_bc;
+    const int64_t nmax = std::max<int64_t>(std::max(na, nbs), 1);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += up256(bytes); return at; };
     L.status = take(256);
     L.nres = residual_blocks(n_int, n_bc);
     L.loss_part = take(sizeof(double) * 2 * (size_t)L.nres);
-    L.sv_int = take(E * (size_t)saved_elems(ni, 5, n_int));
-    L.jets_int = take(E * 5 * (size_t)n_int);
-    L.sv_bc = take(E * (size_t)saved_elems(ni, 1, n_bc));
-    L.ubc = take(E * (size_t)n_bc);
-    L.seed_int = take(E * 5 * (size_t)n_int);
-    L.seed_bc = take(E * (size_t)n_bc);
+    L.xall = take(L.merged ? E * 2 * (size_t)na : 0);
+    L.sv_int = take(E * (size_t)saved_elems(ni, 5, na));
+    L.jets_int = take(E * 5 * (size_t)na);
+    L.sv_bc = take(E * (size_t)saved_elems(ni, 1, nbs));
+    L.ubc = take(E * (size_t)nbs);
+    L.seed_int = take(E * 5 * (size_t)na);
+    L.seed_bc = take(E * (size_t)nbs);
     L.bars0 = take(E * 5 * (size_t)ni.maxw * nmax);
     L.bars1 = take(E * 5 * (size_t)ni.maxw * nmax);
-    L.bbars0 = take(E * (size_t)ni.maxw * n_bc);
-    L.bbars1 = take(E * (size_t)ni.maxw * n_bc);
-    L.part_elems = part_elems_total(ni, n_int, n_bc);
+    L.bbars0 = take(E * (size_t)ni.maxw * nbs);
+    L.bbars1 = take(E * (size_t)ni.maxw * nbs);
+    L.part_elems = part_elems_total(ni, na, nbs);
     L.part = take(E * (size_t)L.part_elems);
     L.wdn = take(wdn_offset(ni, ni.L));
     L.total = o;
@@ -395,7 +429,7 @@ struct RevSet {
 
 template <typename T>
 int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const int64_t *off, T *part,
-                hipStream_t st, bool bc, const char *wdn, hipEvent_t mark = nullptr, int mark_layer = -1)
+                hipStream_t st, bool bc, const char *wdn)
 {
     const GridP<T> g = make_grid<T>(ni);
     const T *ybar = S.seed;
@@ -419,8 +453,6 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             }
         }
         if (e != hipSuccess) return hip_fail(e, "weight-gradient launch");
-        if (mark && l == mark_layer && (e = hipEventRecord(mark, st)) != hipSuccess)
-            return hip_fail(e, "event record");
         if (l == 0) break;
         T *zbar = (ybar == S.bar0) ? S.bar1 : S.bar0;
         {
@@ -442,16 +474,26 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
     return HRKAN_OK;
 }
 
-// Reverse pass of up to two point sets sharing W. Layer l's partial region
-// holds all slices of set 0, then all of set 1; with a fork the second set
-// runs on the side stream. Each gradient element is summed over its slices in
-// that fixed order. With a fork, layers 1.. are reduced on the side stream as
-// soon as both sets have written them (concurrent with the first set's last
-// input bars and layer-0 slices); layer 0, or every layer without a fork, at
-// the end on the caller's stream.
+// Loss partials to be summed by the gradient-reduction launch.
+struct LossTail {
+    const double *part;
+    int nblk;
+    double inv_int, inv_bc, alpha;
+    double *out;
+    uint32_t *status;
+};
+
+// Reverse pass of up to two point sets sharing W: set 0 on st, set 1 on st1
+// (st itself, or the side stream of `fk`, which then starts from fk->fork as
+// recorded by the caller and is joined back before the reduction). Layer l's
+// partial region holds all slices of set 0, then all of set 1. Every layer is
+// reduced in one launch at the end, each element summed over its slices in
+// that fixed order; with `loss`, one more block of the same launch sums the
+// loss partials.
 template <typename T>
 int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, int nsets,
-                 T *const *gW, int accumulate, T *part, hipStream_t st, Fork *fk, const char *wdn)
+                 T *const *gW, int accumulate, T *part, hipStream_t st, hipStream_t st1, Fork *fk,
+                 const char *wdn, const LossTail *loss)
 {
     const int64_t n0 = nsets > 0 ? sets[0].n : 0, n1 = nsets > 1 ? sets[1].n : 0;
     int64_t base[HRKAN_MAX_LAYERS], off0[HRKAN_MAX_LAYERS], off1[HRKAN_MAX_LAYERS];
@@ -466,36 +508,38 @@ int reverse_impl(const NetInfo &ni, const T *const *W, const RevSet<T> *sets, in
         tot[l] = s0 + s1;
         o += part_layer_elems(ni, l, n0, n1);
     }
-    const bool split = fk && n0 > 0 && n1 > 0;
-    const bool early = split && ni.L >= 2;
-    // a layer without slices gets zeros, or is left as it is when accumulating
-    auto reduce = [&](int l0, int l1, hipStream_t rs) -> int {
-        ReduceTable<T> tab{};
-        tab.L = l1 - l0;
-        for (int l = l0; l < l1; ++l) {
-            tab.part[l - l0] = part + base[l];
-            tab.nsplit[l - l0] = tot[l];
-            tab.count[l - l0] = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
-            tab.out[l - l0] = gW[l];
-        }
-        hipError_t e;
-        {
-            ProfScope ps("reduce", -1, rs);
-            e = launch_reduce_layers<T>(tab, accumulate, rs);
-        }
-        return e == hipSuccess ? HRKAN_OK : hip_fail(e, "gradient reduction launch");
-    };
-    if (split) TRY(fork_to(fk, st));
-    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, split ? fk->side : st, true, wdn));
-    if (n0 > 0)
-        TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false, wdn, early ? fk->mid : nullptr, 1));
-    if (early) {
-        const hipError_t e = hipStreamWaitEvent(fk->side, fk->mid, 0);
+    if (n0 > 0) TRY(reverse_set<T>(ni, W, sets[0], off0, part, st, false, wdn));
+    if (st1 != st) {
+        const hipError_t e = hipStreamWaitEvent(st1, fk->fork, 0);
         if (e != hipSuccess) return hip_fail(e, "stream wait");
-        TRY(reduce(1, ni.L, fk->side));
     }
-    if (split) TRY(join_from(fk, st));
-    return reduce(0, early ? 1 : ni.L, st);
+    if (n1 > 0) TRY(reverse_set<T>(ni, W, sets[1], off1, part, st1, true, wdn));
+    if (st1 != st) TRY(join_from(fk, st));
+    // a layer without slices gets zeros, or is left as it is when accumulating
+    ReduceTable<T> tab{};
+    tab.L = ni.L;
+    for (int l = 0; l < ni.L; ++l) {
+        tab.part[l] = part + base[l];
+        tab.nsplit[l] = tot[l];
+        tab.count[l] = (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
+        tab.out[l] = gW[l];
+    }
+    if (loss) {
+        tab.loss_part = loss->part;
+        tab.loss_nblk = loss->nblk;
+        tab.inv_int = loss->inv_int;
+        tab.inv_bc = loss->inv_bc;
+        tab.alpha = loss->alpha;
+        tab.loss_out = loss->out;
+        tab.status = loss->status;
+    }
+    hipError_t e;
+    {
+        ProfScope ps("reduce", -1, st);
+        e = launch_reduce_layers<T>(tab, accumulate, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+    return HRKAN_OK;
 }
 
 int check_ws(void *ws, size_t ws_bytes, size_t need)
@@ -684,18 +728,14 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
         RevSet<double> s{ch, (const double *)x, n, (const double *)seed, (const double *)saved,
                          (double *)(w + L.bars0), (double *)(w + L.bars1)};
         return reverse_impl<double>(ni, (const double *const *)W, &s, 1, (double *const *)gW_out,
-                                    accumulate, (double *)(w + L.part), stream, nullptr, nullptr);
+                                    accumulate, (double *)(w + L.part), stream, stream, nullptr, nullptr, nullptr);
     }
     RevSet<float> s{ch, (const float *)x, n, (const float *)seed, (const float *)saved,
                     (float *)(w + L.bars0), (float *)(w + L.bars1)};
     if (n > 0) TRY(prep_dense(ni, (const float *const *)W, w + L.wdn, stream));
     return reverse_impl<float>(ni, (const float *const *)W, &s, 1, (float *const *)gW_out, accumulate,
-                               (float *)(w + L.part), stream, nullptr, w + L.wdn);
+                               (float *)(w + L.part), stream, stream, nullptr, w + L.wdn, nullptr);
 }
-
-// Interior points times the widest hidden layer up to which the step runs
-// the two point sets concurrently (65,536 x 32 overlaps; 262,144 x 64 does not).
-constexpr int64_t OVERLAP_MAX_WORK = (int64_t)4 << 20;
 
 int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
                const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
@@ -732,29 +772,58 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         char *wdn = w + L.wdn;
         if constexpr (std::is_same<T, float>::value)
             if (ni_ + nb_ > 0) TRY(prep_dense(ni, (const float *const *)W, wdn, stream));
-        // Boundary set on a side stream, concurrent with the interior set,
-        // when the interior's launches are short: overlapping them hides
-        // launch gaps. The hidden-layer launches of a larger set fill the GPU
-        // in one round of blocks, and any kernel beside them pushes some of
-        // those blocks into a second round, which costs more than the
-        // overlap gains; there both sets run on the caller's stream, as they
-        // do while per-launch profiling is on (each launch's events then
-        // time that launch alone).
-        int wmax = 0;
-        for (int l = 1; l < ni.L; ++l) wmax = std::max(wmax, ni.w[l]);
-        const bool overlap = ni_ > 0 && nb_ > 0 && !prof_on() && ni_ * (int64_t)wmax <= OVERLAP_MAX_WORK;
+        double *partials = (double *)(w + L.loss_part);
+        hipError_t e;
+        if (L.merged) {
+            // one set: interior points, then boundary points (merged_sets)
+            const int64_t na = ni_ + nb_;
+            T *xa = (T *)(w + L.xall);
+            e = launch_concat_points<T>((const T *)pts->x_int, ni_, (const T *)pts->x_bc, nb_, xa, stream);
+            if (e != hipSuccess) return hip_fail(e, "point concatenation launch");
+            TRY(forward_impl<T>(ni, chi, (const T *const *)W, xa, na, jets, sv_int, nullptr, nullptr, stream,
+                                false, wdn));
+            const int rb = residual_blocks_of(na);
+            {
+                ProfScope ps("residual", -1, stream);
+                e = launch_residual_merged<T>(pp, chi.C(), jets, (const T *)pts->x_int, ni_,
+                                              (const T *)pts->g_bc, nb_, seed_int, partials, rb, stream);
+            }
+            if (e != hipSuccess) return hip_fail(e, "residual launch");
+            const LossTail lt{partials, rb, 1.0 / (double)ni_, 1.0 / (double)nb_, pde->alpha, loss_out,
+                              (uint32_t *)w};
+            const RevSet<T> s{chi, xa, na, seed_int, sv_int, (T *)(w + L.bars0), (T *)(w + L.bars1)};
+            return reverse_impl<T>(ni, (const T *const *)W, &s, 1, (T *const *)gW_out, 0, (T *)(w + L.part),
+                                   stream, stream, nullptr, wdn, &lt);
+        }
+        // two sets: the boundary set on a side stream (overlap_sets; not while
+        // per-launch profiling is on, whose events then time each launch
+        // alone), forked before the forward pass and again after the
+        // residual, joined after each pass. The interior set's launches are
+        // enqueued first: it is the longer chain.
         Fork *fk = nullptr;
-        if (overlap) TRY(get_fork(stream, &fk));
+        if (overlap_sets(ni, ni_, nb_) && !prof_on()) TRY(get_fork(stream, &fk));
+        hipStream_t sb = fk ? fk->side : stream;
+        // no gradient needs the loss value: the gradient reduction's launch
+        // sums it too
+        const LossTail lt{partials,
+                          L.nres,
+                          ni_ > 0 ? 1.0 / (double)ni_ : 0.0,
+                          nb_ > 0 ? 1.0 / (double)nb_ : 0.0,
+                          pde->alpha,
+                          loss_out,
+                          (uint32_t *)w};
+        RevSet<T> sets[2] = {
+            {chi, (const T *)pts->x_int, ni_, seed_int, sv_int, (T *)(w + L.bars0), (T *)(w + L.bars1)},
+            {chb, (const T *)pts->x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
+        };
         if (fk) TRY(fork_to(fk, stream));
-        if (nb_ > 0)
-            TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
-                                nullptr, nullptr, fk ? fk->side : stream, true, wdn));
         if (ni_ > 0)
             TRY(forward_impl<T>(ni, chi, (const T *const *)W, (const T *)pts->x_int, ni_, jets, sv_int,
                                 nullptr, nullptr, stream, false, wdn));
+        if (nb_ > 0)
+            TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
+                                nullptr, nullptr, sb, true, wdn));
         if (fk) TRY(join_from(fk, stream));
-        double *partials = (double *)(w + L.loss_part);
-        hipError_t e;
         {
             ProfScope ps("residual", -1, stream);
             e = launch_residual<T>(pp, chi.C(), jets, (const T *)pts->x_int, ni_, ubc,
@@ -762,21 +831,11 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
                                    L.nres, stream);
         }
         if (e != hipSuccess) return hip_fail(e, "residual launch");
-        // no gradient needs the loss value: with a fork its final sum runs on
-        // the side stream, beside the interior set's reverse pass
-        if (fk) TRY(fork_to(fk, stream));
-        {
-            hipStream_t ls = fk ? fk->side : stream;
-            ProfScope ps("loss", -1, ls);
-            e = launch_loss_final(partials, L.nres, ni_, nb_, pde->alpha, loss_out, (uint32_t *)w, ls);
+        if (fk) {
+            if ((e = hipEventRecord(fk->fork, stream)) != hipSuccess) return hip_fail(e, "event record");
         }
-        if (e != hipSuccess) return hip_fail(e, "loss launch");
-        RevSet<T> sets[2] = {
-            {chi, (const T *)pts->x_int, ni_, seed_int, sv_int, (T *)(w + L.bars0), (T *)(w + L.bars1)},
-            {chb, (const T *)pts->x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
-        };
         return reverse_impl<T>(ni, (const T *const *)W, sets, 2, (T *const *)gW_out, 0,
-                               (T *)(w + L.part), stream, fk, wdn);
+                               (T *)(w + L.part), stream, sb, fk, wdn, &lt);
     };
     if (ni.dtype == HRKAN_F64) return run(double{});
     return run(float{});

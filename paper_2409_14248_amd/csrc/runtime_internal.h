@@ -24,6 +24,8 @@ struct NetInfo {
 
 // Byte offsets of the workspace regions.
 struct WsLayout {
+    bool merged;                // both point sets as one (merged_sets)
+    size_t xall;                // the merged set's points
     size_t status, loss_part, sv_int, jets_int, sv_bc, ubc, seed_int, seed_bc;
     size_t bars0, bars1, bbars0, bbars1, part;
     size_t wdn;                 // BF16 weight copies of the dense-kernel layers
@@ -43,14 +45,15 @@ int64_t saved_elems(const NetInfo &ni, int C, int64_t n);
 int dw_splits(const NetInfo &ni, int l, int64_t n);
 int64_t part_layer_elems(const NetInfo &ni, int l, int64_t n_a, int64_t n_b);
 
-// Side stream and events of one caller stream (see get_fork).
+// Whether a training step runs its interior and boundary sets as one set.
+bool merged_sets(const NetInfo &ni, int64_t n_int, int64_t n_bc);
 struct Fork {
     hipStream_t side;
-    hipEvent_t fork, join, mid;   // mid: the caller's stream part-way through a pass
+    hipEvent_t fork, join;
 };
 int get_fork(hipStream_t st, Fork **out);
-int fork_to(Fork *f, hipStream_t st);      // side waits for st's work so far
-int join_from(Fork *f, hipStream_t st);    // st waits for side's work so far
+int fork_to(Fork *f, hipStream_t st);
+int join_from(Fork *f, hipStream_t st);
 bool use_bs32(const NetInfo &ni, int l);
 bool use_dn(const NetInfo &ni, int l);
 size_t wdn_offset(const NetInfo &ni, int l);   // layer l's copies within the wdn region

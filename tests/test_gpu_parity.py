@@ -110,7 +110,12 @@ def test_step_other_orders(k, m, dtype):
 # ---------------------------------------------------------------------------
 # FP32 path
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n_int,n_bc", [(4096 + 37, 256), (1, 4), (63, 0), (0, 100), (65, 8)])
+# The step runs the two sets as one set, on two streams, or one after the
+# other by the interior points times the widest hidden layer (32 here):
+# 4,133 and 65 points merge, 40,000 overlap, 131,077 go one after the other;
+# a set without boundary points never merges
+@pytest.mark.parametrize("n_int,n_bc", [(4096 + 37, 256), (1, 4), (63, 0), (0, 100), (65, 8),
+                                        (40000, 300), (131072 + 5, 700)])
 def test_step_burgers_c2_shape_f32_sizes(n_int, n_bc):
     wl = WL.WORKLOADS["burgers_c2"]
     pr = WL.make_problem(wl, n_int=n_int, n_bc=n_bc)
