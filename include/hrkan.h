@@ -193,7 +193,13 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
 /* One full training step: forward jets at both point sets, residual, loss
  * (loss_out device double[3] = {L, L_pde, L_bc}) and gW_out[l] = dL/dW[l]
  * (overwritten). The interior mask is the PDE's (Poisson: 5 channels,
- * Burgers: 4); boundary points carry the value only. */
+ * Burgers: 4); only the value enters the boundary loss. Execution depends on
+ * the set sizes (the results do not, up to rounding): small sets run as one
+ * set, medium ones put the boundary set on a second stream that the library
+ * creates for `stream` on first use (default priority; every fork is joined
+ * back into `stream` within the call's work, and under graph capture the
+ * fork and join become graph edges), large ones run on `stream` alone.
+ * hrkan_workspace_bytes gives the size for the same counts. */
 int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
                const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
                size_t ws_bytes, hipStream_t stream);
