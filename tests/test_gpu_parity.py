@@ -290,12 +290,15 @@ def test_autograd_functions_match_step(dtype):
         assert relerr(w.grad.double().cpu().numpy(), b) < 1e-5
 
 
+# 6,000 points run as one merged set, 40,000 on two streams (the capture
+# then holds the fork and join)
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_graph_replay_matches_eager_step(dtype):
+@pytest.mark.parametrize("n_int", [6000, 40000])
+def test_graph_replay_matches_eager_step(dtype, n_int):
     """The step captured in a HIP graph gives the eager result on every
     replay, with eager work on the same buffers in between (BF16: including
     the per-call BF16 weight copies of the dense kernels)."""
-    pr = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=6000, n_bc=400)
+    pr = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=n_int, n_bc=400)
     st = H.Step(pr, dtype)
     loss0, gW0 = st()
     torch.cuda.synchronize()
