@@ -48,13 +48,10 @@ hipError_t launch_dw_generic(ChanCfg ch, bool first, const T *zin, const T *ybar
 int dw_generic_splits(int64_t n, LayerShape ls);
 size_t dw_generic_lds_bytes(int elem, int C, int nb);
 
-// out[e] (+)= sum_s part[s][e] for e < count, s in fixed order.
-template <typename T>
-hipError_t launch_reduce_splits(const T *part, int nsplit, int64_t count, T *out, int accumulate,
-                                hipStream_t st);
 
-// The same for every layer of a network in one launch (blk0 is filled in by
-// the launcher).
+// gW[l][e] (+)= sum_s part_l[s][e] for every layer of a network in one
+// launch, each element's slices summed in a fixed order in FP64 (blk0 is
+// filled in by the launcher).
 template <typename T>
 struct ReduceTable {
     int L;

@@ -431,48 +431,11 @@ __device__ __forceinline__ void loss_block(const double *__restrict__ partials, 
 
 constexpr int RD_EB = 32, RD_SL = NT / RD_EB;
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_reduce_splits(const T *__restrict__ part, int nsplit,
-                                                      int64_t count, T *__restrict__ out,
-                                                      int accumulate)
-{
-    __shared__ double sh[RD_SL][RD_EB];
-    const int el = threadIdx.x % RD_EB, sl = threadIdx.x / RD_EB;
-    const int64_t e = (int64_t)blockIdx.x * RD_EB + el;
-    double s = 0.0;
-    if (e < count) {
-        // slices sl, sl + RD_SL, ... in increasing order; 8 loads in flight
-        int k = sl;
-        for (; k + 7 * RD_SL < nsplit; k += 8 * RD_SL) {
-            T v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(k + u * RD_SL) * count + e];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += (double)v[u];
-        }
-        for (; k < nsplit; k += RD_SL) s += (double)part[(int64_t)k * count + e];
-    }
-    sh[sl][el] = s;
-    __syncthreads();
-    if (sl == 0 && e < count) {
-        double t = accumulate ? (double)out[e] : 0.0;
-        for (int k = 0; k < RD_SL; ++k) t += sh[k][el];
-        out[e] = (T)t;
-    }
-}
-
-template <typename T>
-hipError_t launch_reduce_splits(const T *part, int nsplit, int64_t count, T *out, int accumulate,
-                                hipStream_t st)
-{
-    if (count <= 0) return hipSuccess;
-    k_reduce_splits<T><<<(unsigned)((count + RD_EB - 1) / RD_EB), NT, 0, st>>>(part, nsplit, count, out,
-                                                                               accumulate);
-    return hipGetLastError();
-}
-
 // Every layer's reduction in one launch: blocks [blk0[l], blk0[l+1]) take
-// layer l, each element summed over its slices exactly as k_reduce_splits.
+// layer l. A block takes RD_EB elements: its RD_SL slice lanes add slices
+// sl, sl + RD_SL, ... in increasing order (8 loads in flight) in FP64, and
+// the lanes' sums are added in lane order, so each element has one fixed
+// summation order.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_reduce_layers(ReduceTable<T> tab, int accumulate)
 {
@@ -780,7 +743,6 @@ hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, in
                                              int64_t, LayerShape, const GridP<T> &, hipStream_t); \
     template hipError_t launch_dw_generic<T>(ChanCfg, bool, const T *, const T *, T *, int,      \
                                              int64_t, LayerShape, const GridP<T> &, hipStream_t); \
-    template hipError_t launch_reduce_splits<T>(const T *, int, int64_t, T *, int, hipStream_t);  \
     template hipError_t launch_reduce_layers<T>(ReduceTable<T>, int, hipStream_t);                 \
     template hipError_t launch_adam<T>(AdamTable<T>, int64_t *, double, double, double, double, hipStream_t); \
     template hipError_t launch_residual<T>(const PdeParams &, int, const T *, const T *, int64_t, \
