@@ -688,10 +688,15 @@ __global__ __launch_bounds__(NT8, (fwd_waves<O0, O1, NQ>())) void k_dx_bs(const 
 // current one is computed.
 // ---------------------------------------------------------------------------
 // points per staged chunk (a divisor of the block size): short per-point
-// work (2 inputs per wave) takes large chunks so the global loads stay ahead
-// of the compute -- 64 points for 32-output layers; else 16, or 8 for wide
-// 5-channel tiles (LDS)
-template <int NQ, int II, int C> constexpr int dw_pc() { return NQ >= 32 ? ((II == 2 && C <= 4) ? 16 : 8) : (II == 2 && NQ <= 8) ? 64 : 16; }
+// work (2 inputs per wave) takes larger chunks so the global loads stay ahead
+// of the compute -- 32 points for 32-output layers (64 would double the
+// block's LDS and halve its blocks per CU: no faster on 65,536 points, slower
+// on 4,096); else 16, or 8 for wide 5-channel tiles (LDS)
+constexpr int dw_pc_of(int NQ, int II, int C)
+{
+    return NQ >= 32 ? ((II == 2 && C <= 4) ? 16 : 8) : (II == 2 && NQ <= 8) ? 32 : 16;
+}
+template <int NQ, int II, int C> constexpr int dw_pc() { return dw_pc_of(NQ, II, C); }
 
 template <int O0, int O1, bool FIRST, int NQ, int II, int S>
 __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
@@ -927,7 +932,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
 static size_t dw_bs_lds(int C, int nb, int N, int II)
 {
     const int CP = C <= 4 ? 4 : 8, IB = 4 * II, JC = 16 / II;
-    const int PC = N >= 128 ? ((II == 2 && C <= 4) ? 16 : 8) : (II == 2 && N <= 32) ? 64 : 16;
+    const int PC = dw_pc_of(N / 4, II, C);
     return sizeof(float) *
            ((size_t)IB * (nb * N + 4 * JC) + (size_t)PC * (IB * CP + 4) + (size_t)PC * (N * CP + 4));
 }
