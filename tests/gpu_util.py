@@ -72,3 +72,11 @@ def expand(jets_c: np.ndarray, mask: int) -> np.ndarray:
     for c, s in enumerate(SLOTS_OF_MASK[mask]):
         out[s] = jets_c[c]
     return out
+
+
+def bf16_round(a):
+    """Round-to-nearest-even of FP32 values to the BF16 grid (as float64)."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)

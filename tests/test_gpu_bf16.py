@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 from conftest import relerr
-from gpu_util import SLOTS_OF_MASK, gpu_step, oracle_step, to_dev
+from gpu_util import SLOTS_OF_MASK, bf16_round, gpu_step, oracle_step, to_dev
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
 
@@ -23,14 +23,6 @@ pytestmark = pytest.mark.gpu
 
 TOL = 2e-2
 FLOOR_FACTOR = 3.0
-
-
-def bf16_round(a):
-    """Round-to-nearest-even of FP32 values to the BF16 grid (as float64)."""
-    f = np.ascontiguousarray(a, dtype=np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def bf16_floor_step(pr, S, with_model=False):
