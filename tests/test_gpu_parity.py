@@ -107,6 +107,31 @@ def test_step_other_orders(k, m, dtype):
             assert relerr(a, b) < gt
 
 
+# The deepest and widest networks the interface takes: 8 layers, one of them
+# HRKAN_MAX_WIDTH = 1024 wide (the wide layers run on the generic kernels,
+# the 32-wide ones on the matrix-core kernels); 300 points run as one merged
+# set, 2,000 on two streams.
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n_int", [300, 2000])
+def test_step_max_layers_and_width(dtype, n_int):
+    net = WL.Net((2, 8, 1024, 16, 32, 32, 8, 24, 1), G=5)
+    assert net.n_layers == H.MAX_LAYERS
+    wl = WL.Workload("deep", net, WL.Pde(WL.POISSON2D), n_int, 40, dtype, WL.SEED_BASE + 90)
+    pr = WL.make_problem(wl)
+    loss, gW, ws = gpu_step(pr, dtype)
+    assert H.read_status(ws) == 0
+    if dtype == "f64":
+        ref = oracle_step(pr, "f64")
+        assert relerr(loss, ref["loss"]) < 1e-10
+        for a, b in zip(gW, ref["gW"]):
+            assert relerr(a, b) < 1e-10
+    else:
+        ref, gl, gg = fp32_step_gates(pr)
+        assert relerr(loss, ref["loss"]) < gl
+        for a, b, gt in zip(gW, ref["gW"], gg):
+            assert relerr(a, b) < gt
+
+
 # ---------------------------------------------------------------------------
 # FP32 path
 # ---------------------------------------------------------------------------
