@@ -17,7 +17,7 @@ import torch
 
 import oracle as O
 from conftest import relerr
-from gpu_util import (expand, gpu_forward, gpu_step, oracle_step, saved_blocks, to_dev)
+from gpu_util import (NP_DTYPE, expand, gpu_forward, gpu_step, oracle_step, saved_blocks, to_dev)
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
 
@@ -129,6 +129,56 @@ def test_step_max_layers_and_width(dtype, n_int):
         ref, gl, gg = fp32_step_gates(pr)
         assert relerr(loss, ref["loss"]) < gl
         for a, b, gt in zip(gW, ref["gW"], gg):
+            assert relerr(a, b) < gt
+
+
+def special_points():
+    """Coordinates on the knots of the c2 grid (G = 10 on [-1, 1], h = 0.2,
+    supports extended by k h beyond each end: Sec. 2.2), one FP32 unit on
+    either side of them, on the grid ends and far outside it, paired in
+    every combination of a short list."""
+    h = 0.2
+    knots = -1.0 + h * np.arange(-3, 14)
+    eps = np.float32(np.finfo(np.float32).eps)
+    v = np.concatenate([knots, knots * (1 + eps), knots * (1 - eps),
+                        [-1.0, 1.0, 0.0, 1.6, -1.6, 1.61, -1.61, 3.0, -10.0, 1e6]])
+    v = v.astype(np.float32).astype(np.float64)
+    short = v[::3]
+    xs, ts = np.meshgrid(v, short, indexing="ij")
+    return np.stack([xs.ravel(), ts.ravel()], axis=1)
+
+
+# The window and support tests of every kernel at the points where they
+# switch: inputs on knots (the basis is C^2, Eq. 2 with m = 4, so either
+# window gives the same values), on the ends of the extended supports and
+# far outside them (all-zero basis).
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_step_at_knots_and_outside_the_grid(dtype):
+    base = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=8, n_bc=8)
+    x = special_points()
+    n = x.shape[0]
+    xb = x[: n // 4]
+    pr = WL.Problem(base.net, base.pde, base.W, x, xb, np.sin(np.pi * xb[:, 0]))
+    q = pr.rounded(NP_DTYPE[dtype])
+    mask = H.MASK_BURGERS
+    jets, *_ = gpu_forward(pr, dtype, q.x_int, mask)
+    ref = O.forward(q.net, q.W, q.x_int)
+    loss, gW, ws = gpu_step(pr, dtype)
+    assert H.read_status(ws) == 0
+    sref = oracle_step(pr, dtype)
+    if dtype == "f64":
+        for c, sl in enumerate(__import__("gpu_util").SLOTS_OF_MASK[mask]):
+            assert relerr(jets[c], ref[sl]) < 1e-10, c
+        assert relerr(loss, sref["loss"]) < 1e-10
+        for a, b in zip(gW, sref["gW"]):
+            assert relerr(a, b) < 1e-10
+    else:
+        gate = max(TOL["f32"], FLOOR_FACTOR * fp32_floor(pr, q.x_int, mask))
+        for c, sl in enumerate(__import__("gpu_util").SLOTS_OF_MASK[mask]):
+            assert relerr(jets[c], ref[sl]) < gate, (c, relerr(jets[c], ref[sl]), gate)
+        _, gl, gg = fp32_step_gates(pr)
+        assert relerr(loss, sref["loss"]) < gl
+        for a, b, gt in zip(gW, sref["gW"], gg):
             assert relerr(a, b) < gt
 
 
