@@ -902,6 +902,24 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         if (pc + PC < pe) load(pc + PC);         // next chunk in flight during this one
         const int npts = (int)min<int64_t>(PC, pe - pc);
         int pp = wp;
+        // wide layers with one point group: points in fours, so that the
+        // next points' operands are prepared while earlier ones update
+        // (c3: 2.02 -> 1.93 ms per launch). Narrow layers keep pairs: the
+        // registers of four points would halve the blocks per CU of their
+        // smaller-LDS instances.
+        if constexpr (NQ >= 16)
+            if (WP == 1)
+                for (; pp + 3 < npts; pp += 4) {
+                    Pt a, b, c, d;
+                    prepare(pp, a);
+                    prepare(pp + 1, b);
+                    prepare(pp + 2, c);
+                    prepare(pp + 3, d);
+                    update(a);
+                    update(b);
+                    update(c);
+                    update(d);
+                }
         for (; pp + WP < npts; pp += 2 * WP) {
             Pt a, b;
             prepare(pp, a);
