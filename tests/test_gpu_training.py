@@ -42,10 +42,13 @@ def test_adam_matches_oracle(dtype, tol):
     assert int(t.item()) == 3
 
 
-def test_trainer_graph_replays_match_eager_epochs():
+# the paper's Poisson instance runs its step as one merged set; 40,000
+# Burgers points run the two point sets on two streams inside the graph
+@pytest.mark.parametrize("name,n_int", [("poisson_paper", None), ("burgers_c2", 40000)])
+def test_trainer_graph_replays_match_eager_epochs(name, n_int):
     """Twenty epochs replayed from one captured graph give bit for bit the
     weights of twenty eager epochs (the step count lives in device memory)."""
-    pr = WL.make_problem(WL.WORKLOADS["poisson_paper"])
+    pr = WL.make_problem(WL.WORKLOADS[name], n_int=n_int, n_bc=(1000 if n_int else None))
     a = H.Trainer(pr, "f32", lr=1e-2)
     ha = a.run(20, graph=False, record_every=5)
     b = H.Trainer(pr, "f32", lr=1e-2)
