@@ -767,9 +767,10 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
     // every k, PC dividing NT) of row e / PC = c N + j, so the k-th load is
     // the first one plus k (NT / PC) rows
     static_assert(NT % PC == 0, "chunk size must divide the block");
+    // a launch may split the outputs over gridDim.z blocks: this block takes
+    // outputs J0 .. J0 + N - 1 of NTOT
+    const int NTOT = N * (int)gridDim.z, J0 = N * (int)blockIdx.z;
     const int ypp = threadIdx.x % PC, yrow0 = threadIdx.x / PC;
-    const float *ysrc = ybar + (int64_t)yrow0 * n + ypp;
-    const int64_t ystep = (int64_t)(NT / PC) * n;
     float rj[RJ], ry[RY];
     auto load = [&](int64_t pc) {
 #pragma unroll
@@ -793,7 +794,10 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const bool ok = yin && threadIdx.x + k * NT < EY;
-            const float y = ysrc[ok ? k * ystep + pc : -(int64_t)ypp];   // a dead lane reads its first row
+            // this block's row c N + j is row c NTOT + J0 + j of the bars
+            const int row = yrow0 + k * (NT / PC);
+            const int grow = row + (row / N) * (NTOT - N) + J0;
+            const float y = ybar[ok ? (int64_t)grow * n + ypp + pc : 0];   // a dead lane reads the first element
             ry[k] = ok ? y : 0.f;
         }
     };
@@ -934,7 +938,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         }
     }
     __syncthreads();
-    const int64_t KN = (int64_t)win * nb * N;
+    const int64_t KN = (int64_t)win * nb * NTOT;
     const int gcopy = IBe * IS;
     for (int e = threadIdx.x; e < IBe * nb * N; e += NT) {
         const int row = e / N, col = e % N;
@@ -943,7 +947,7 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         const int at = il * IS + b * GS + col;
         float sum = sG[at];
         for (int w = 1; w < WP; ++w) sum += sG[w * gcopy + at];
-        part[split * KN + (int64_t)(i0 * nb + row) * N + col] = sum;
+        part[split * KN + (int64_t)(i0 * nb + row) * NTOT + J0 + col] = sum;
     }
 }
 
@@ -1419,6 +1423,16 @@ static DwTile dw_tile(LayerShape ls, int C, int ii_override = 0)
     return {ii, wi};
 }
 
+// Output blocks of the weight-gradient launch: a 128-output layer is split
+// over two blocks (grid z) of 64 outputs each, which halves a block's LDS
+// gradient copy and staged bars, so that two blocks fit a CU instead of one.
+static int dw_jsplit(LayerShape ls) { return ls.wout == 128 ? 2 : 1; }
+static LayerShape dw_block_shape(LayerShape ls)
+{
+    ls.wout /= dw_jsplit(ls);
+    return ls;
+}
+
 int dw_bs32_splits(int64_t n, LayerShape ls)
 {
     if (n <= 0) return 0;
@@ -1428,7 +1442,7 @@ int dw_bs32_splits(int64_t n, LayerShape ls)
     if (ls.wout == 1) {
         tiles = (ls.win + NT / DL_SL - 1) / (NT / DL_SL);
     } else {
-        const DwTile t = dw_tile(ls, 4);
+        const DwTile t = dw_tile(dw_block_shape(ls), 4);
         const int ib = std::max(1, t.II * t.WI);
         tiles = (ls.win + ib - 1) / ib;
     }
@@ -1447,16 +1461,17 @@ hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float 
         });
         return hipGetLastError();
     }
-    const DwTile tl = dw_tile(ls, ch.C(), dw_ii_override);
+    const LayerShape lb = dw_block_shape(ls);
+    const DwTile tl = dw_tile(lb, ch.C(), dw_ii_override);
     if (tl.II == 0) return hipErrorInvalidValue;
     const int ibe = tl.II * tl.WI;
-    const dim3 grid((unsigned)((ls.win + ibe - 1) / ibe), (unsigned)nsplit);
+    const dim3 grid((unsigned)((ls.win + ibe - 1) / ibe), (unsigned)nsplit, (unsigned)dw_jsplit(ls));
     const int wi = tl.WI;
     HRK_CH_S_SWITCH(ch, S, {
-        HRK_NQ_SWITCH(ls.wout, {
+        HRK_NQ_SWITCH(lb.wout, {
             HRK_II_SWITCH(tl.II, {
                 if constexpr (16 / II <= NQ) {
-                    const size_t sh = dw_bs_lds(ch.C(), ls.nb, ls.wout, II);
+                    const size_t sh = dw_bs_lds(ch.C(), lb.nb, lb.wout, II);
                     if (first) {
                         auto kf = k_dw_bs<O0, O1, true, NQ, II, S>;
                         set_lds_limit((const void *)kf);
