@@ -1423,10 +1423,12 @@ static DwTile dw_tile(LayerShape ls, int C, int ii_override = 0)
     return {ii, wi};
 }
 
-// Output blocks of the weight-gradient launch: a 128-output layer is split
-// over two blocks (grid z) of 64 outputs each, which halves a block's LDS
-// gradient copy and staged bars, so that two blocks fit a CU instead of one.
-static int dw_jsplit(LayerShape ls) { return ls.wout == 128 ? 2 : 1; }
+// Output blocks of the weight-gradient launch: a layer of 64 or 128 outputs
+// is split over two blocks (grid z) of half the outputs each, which halves a
+// block's LDS gradient copy and staged bars (128 outputs: two blocks per CU
+// instead of one; c4 33.2 -> 24.5 ms, c3 1.99 -> 1.90 ms per launch), at the
+// cost of evaluating the features twice.
+static int dw_jsplit(LayerShape ls) { return ls.wout >= 64 ? 2 : 1; }
 static LayerShape dw_block_shape(LayerShape ls)
 {
     ls.wout /= dw_jsplit(ls);
