@@ -66,6 +66,7 @@ extern "C" {
 #define HRKAN_ERR_WORKSPACE (-3)     /* ws_bytes smaller than required */
 #define HRKAN_ERR_DEVICE (-4)        /* a HIP call failed; see hrkan_last_error() */
 #define HRKAN_ERR_PLAN_MISMATCH (-5) /* plan used with another shape or freed */
+#define HRKAN_ERR_HOST_MEMORY (-6)   /* a host allocation failed (plan tables) */
 
 /* bits of the device status word (hrkan_read_status) */
 #define HRKAN_STATUS_NONFINITE 1u    /* a loss partial was NaN or Inf */

@@ -80,12 +80,25 @@ static double round_bar_split(double v) { return g_mode == 2 ? round_feature(v) 
 static double round_bar_hi(double v) { return g_mode == 2 ? to_bf16(to_f32(v)) : v; }
 
 /* one step of a contraction's running sum, acc + w * a; in the rounding
- * model it is rounded to FP32 as an FP32 fused multiply-add would (the
- * product of two FP32 values is exact in double: one rounding of the sum) */
+ * model it is an FP32 fused multiply-add of the operands held in FP32: the
+ * exact value of acc + w * a rounded once to FP32 (C99 fmaf). */
 static double acc_step(double acc, double w, double a)
 {
-    return g_mode == 0 ? acc + w * a : to_f32(acc + w * a);
+    return g_mode == 0 ? acc + w * a : (double)fmaf((float)w, (float)a, (float)acc);
 }
+
+double hro_model_round(int what, double v)
+{
+    switch (what) {
+    case 0: return round_feature(v);
+    case 1: return round_store(v);
+    case 2: return round_bar_split(v);
+    case 3: return round_bar_hi(v);
+    default: return v;
+    }
+}
+
+double hro_model_acc(double acc, double w, double a) { return acc_step(acc, w, a); }
 
 /* ------------------------------------------------------------------ */
 /* grid and basis                                                      */

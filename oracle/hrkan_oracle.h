@@ -10,7 +10,7 @@
  * What it computes (all in double precision, scalar loops, no tiling):
  *   - the HR basis of order m and its derivatives (Sec. 3, Eq. 2),
  *   - the KAN layer as "basis tensor times weight matrix" (Sec. 3, the
- *     matrix-operation remark; Sec. 2.2 for the supports),
+ *     matrix-operation remark; Sec. 2.1-2.2 for the supports),
  *   - forward-mode jets (value, first and second derivative per input
  *     direction) through every layer, as needed by the PDE residuals
  *     (Sec. 4.1 loss, Sec. 4.2 loss),
@@ -128,6 +128,16 @@ int hro_step(const hro_net *net, const hro_pde *pde, const double *const *W,
  *           multiplies a feature (weight gradient).
  * Weights are never rounded here: callers pass already rounded weights. */
 void hro_set_rounding(int mode, int split);
+
+/* The rounding model's primitives under the current mode, exposed so that
+ * tests can pin them against independent FP32/BF16 conversions:
+ *   what 0: a basis feature; 1: a stored layer output or input bar;
+ *   2: an output bar where it multiplies W; 3: an output bar where it
+ *   multiplies a feature.  Mode 0 returns v unchanged. */
+double hro_model_round(int what, double v);
+/* One step acc + w * a of a contraction's running sum (mode >= 1: one FP32
+ * fused multiply-add of the FP32-held operands). */
+double hro_model_acc(double acc, double w, double a);
 
 /* Number of OpenMP threads the oracle runs with. */
 int hro_num_threads(void);

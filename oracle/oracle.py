@@ -33,7 +33,7 @@ def build(force: bool = False) -> str:
     ):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+            ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared",
              "-fno-fast-math", "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
         )
         os.replace(tmp, _LIB)
@@ -86,6 +86,10 @@ def _load():
         lib.hro_num_threads.restype = ctypes.c_int
         lib.hro_set_rounding.argtypes = [ctypes.c_int, ctypes.c_int]
         lib.hro_set_rounding.restype = None
+        lib.hro_model_round.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.hro_model_round.restype = ctypes.c_double
+        lib.hro_model_acc.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.hro_model_acc.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -141,6 +145,19 @@ class rounding:
 
     def __exit__(self, *a):
         _load().hro_set_rounding(0, 1)
+
+
+MODEL_FEATURE, MODEL_STORE, MODEL_BAR_SPLIT, MODEL_BAR_HI = 0, 1, 2, 3
+
+
+def model_round(what: int, v: float) -> float:
+    """One rounding of the current rounding model (see hro_model_round)."""
+    return _load().hro_model_round(int(what), float(v))
+
+
+def model_acc(acc: float, w: float, a: float) -> float:
+    """One accumulation step acc + w * a of the current rounding model."""
+    return _load().hro_model_acc(float(acc), float(w), float(a))
 
 
 def num_threads() -> int:

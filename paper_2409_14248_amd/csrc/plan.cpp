@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <new>
 #include <vector>
 
 #include "batch.h"
@@ -289,22 +290,24 @@ int enqueue(const hrkan_plan *p, const PlanCfg &cfg, hipStream_t st)
     return HRKAN_OK;
 }
 
-// Average time of `reps` enqueues of cfg (after one untimed), in ms.
+// Average time of `reps` enqueues of cfg (after one untimed), in ms. The two
+// events are released on every path.
 int time_cfg(hrkan_plan *p, const PlanCfg &cfg, hipStream_t st, int reps, float *ms)
 {
     int rc = enqueue(p, cfg, st);
     if (rc != HRKAN_OK) return rc;
-    hipEvent_t a, b;
-    PTRY(hipEventCreate(&a));
-    PTRY(hipEventCreate(&b));
-    PTRY(hipEventRecord(a, st));
-    for (int r = 0; r < reps && rc == HRKAN_OK; ++r) rc = enqueue(p, cfg, st);
-    PTRY(hipEventRecord(b, st));
-    PTRY(hipEventSynchronize(b));
-    PTRY(hipEventElapsedTime(ms, a, b));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    for (int r = 0; r < reps && e == hipSuccess && rc == HRKAN_OK; ++r) rc = enqueue(p, cfg, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "plan timing events");
     *ms /= reps;
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
     return rc;
 }
 
@@ -332,9 +335,13 @@ int hrkan_plan_workspace_bytes(const hrkan_net_desc *net, int32_t n_inst, const 
     return HRKAN_OK;
 }
 
-int hrkan_plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_inst, const hrkan_pde_desc *pdes,
+static int plan_build(hrkan_plan *p, const NetInfo &ni, int32_t n_inst, const hrkan_pde_desc *pdes,
                       const void *W_packed, const hrkan_points *pts, double *loss_out, void *gW_packed, void *ws,
-                      size_t ws_bytes, hipStream_t stream)
+                      size_t ws_bytes, const PlanLayout &L, hipStream_t stream);
+
+static int plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_inst, const hrkan_pde_desc *pdes,
+                       const void *W_packed, const hrkan_points *pts, double *loss_out, void *gW_packed, void *ws,
+                       size_t ws_bytes, hipStream_t stream)
 {
     if (!out) return fail(HRKAN_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -370,6 +377,28 @@ int hrkan_plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_ins
     if (ws_bytes < L.total) return fail(HRKAN_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
 
     hrkan_plan *p = new hrkan_plan();
+    p->graph = nullptr;
+    p->exec = nullptr;
+    try {
+        rc = plan_build(p, ni, n_inst, pdes, W_packed, pts, loss_out, gW_packed, ws, ws_bytes, L, stream);
+    } catch (...) {
+        release(p);
+        throw;
+    }
+    if (rc != HRKAN_OK) {
+        release(p);
+        return rc;
+    }
+    *out = p;
+    return HRKAN_OK;
+}
+
+// Fill a new plan: tables, autotuned configuration, captured graph.
+static int plan_build(hrkan_plan *p, const NetInfo &ni, int32_t n_inst, const hrkan_pde_desc *pdes,
+                      const void *W_packed, const hrkan_points *pts, double *loss_out, void *gW_packed, void *ws,
+                      size_t ws_bytes, const PlanLayout &L, hipStream_t stream)
+{
+    int rc = HRKAN_OK;
     p->ni = ni;
     p->n_inst = n_inst;
     p->kind = pdes[0].kind;
@@ -383,13 +412,11 @@ int hrkan_plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_ins
     p->ws = (char *)ws;
     p->ws_bytes = ws_bytes;
     p->L = L;
-    o = 0;
+    int64_t o = 0;
     for (int l = 0; l < ni.L; ++l) {
         p->woff[l] = o;
         o += (int64_t)ni.w[l] * ni.nb * ni.w[l + 1];
     }
-    p->graph = nullptr;
-    p->exec = nullptr;
     if (rc == HRKAN_OK && hipGetDevice(&p->dev) != hipSuccess) rc = fail(HRKAN_ERR_DEVICE, "hipGetDevice");
 
     // autotune: every candidate timed on the caller's buffers
@@ -435,12 +462,19 @@ int hrkan_plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_ins
         }
         if (cs) (void)hipStreamDestroy(cs);
     }
-    if (rc != HRKAN_OK) {
-        release(p);
-        return rc;
+    return rc;
+}
+
+int hrkan_plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_inst, const hrkan_pde_desc *pdes,
+                      const void *W_packed, const hrkan_points *pts, double *loss_out, void *gW_packed, void *ws,
+                      size_t ws_bytes, hipStream_t stream)
+{
+    try {
+        return plan_create(out, net, n_inst, pdes, W_packed, pts, loss_out, gW_packed, ws, ws_bytes, stream);
+    } catch (const std::bad_alloc &) {
+        if (out) *out = nullptr;
+        return fail(HRKAN_ERR_HOST_MEMORY, "host memory exhausted while building the plan");
     }
-    *out = p;
-    return HRKAN_OK;
 }
 
 int hrkan_plan_execute(hrkan_plan *plan, hipStream_t stream)

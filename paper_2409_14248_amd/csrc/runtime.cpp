@@ -577,6 +577,7 @@ const char *hrkan_status_string(int code)
     case HRKAN_ERR_WORKSPACE: return "workspace too small";
     case HRKAN_ERR_DEVICE: return "HIP device error";
     case HRKAN_ERR_PLAN_MISMATCH: return "plan mismatch";
+    case HRKAN_ERR_HOST_MEMORY: return "host memory exhausted";
     default: return "unknown status";
     }
 }

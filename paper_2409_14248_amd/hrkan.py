@@ -33,7 +33,8 @@ MASK_BURGERS = CH_U | CH_X | CH_XX | CH_Y
 MASK_VALUE = CH_U
 STATUS_NONFINITE = 1
 
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_PLAN_MISMATCH = 0, -1, -2, -3, -4, -5
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_PLAN_MISMATCH, ERR_HOST_MEMORY = \
+    0, -1, -2, -3, -4, -5, -6
 
 EXPORTS = [
     "hrkan_net_init", "hrkan_pde_init", "hrkan_mask_channels", "hrkan_saved_bytes",

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 
 def test_status_strings():
     L = H.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.hrkan_status_string(code).decode() != "unknown status"
 
 

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle as O
-from conftest import relerr
+from conftest import check, relerr
 from gpu_util import gpu_step
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
@@ -58,9 +58,38 @@ def test_batched_instance_matches_oracle():
     torch.cuda.synchronize()
     q = probs[1].rounded(np.float32)
     ref = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
-    assert relerr(plan.loss[1].cpu().numpy(), ref["loss"]) < 1e-5
+    check("batched 3-instance inst1 loss", relerr(plan.loss[1].cpu().numpy(), ref["loss"]), 1e-5)
     for l, g in enumerate(plan.layer_grads(1, q.net)):
-        assert relerr(g.double().cpu().numpy(), ref["gW"][l]) < 1e-5, l
+        check(f"batched 3-instance inst1 gW{l}", relerr(g.double().cpu().numpy(), ref["gW"][l]), 1e-5)
+
+
+@pytest.mark.slow
+def test_full_batched_plan_against_oracle():
+    """The 256-instance Burgers batch (nu log-uniform in [1e-3, 1e-1], interior
+    counts uniform in [4,096, 65,536], boundary counts 1/16 of them), with the
+    first instance set to the smallest count of that range and the last to
+    the largest: those two, the instance with the most and the one with the
+    fewest drawn points against the FP64 oracle at the literal 1e-5."""
+    wl = WL.WORKLOADS["burgers_batched_c5"]
+    probs = WL.batched_instances(wl)
+    assert len(probs) == 256
+    for q, n in ((0, 4096), (255, 65536)):
+        probs[q] = WL.make_problem(wl, n_int=n, n_bc=n // 16, seed=wl.seed + 1000 * (q + 1), pde=probs[q].pde)
+    print(f"[case] full batched plan: {sum(p.n_int for p in probs)} interior points", flush=True)
+    plan = H.Plan(probs)
+    plan.execute()
+    torch.cuda.synchronize()
+    assert H.read_status(plan.ws) == 0
+    sizes = [p.n_int for p in probs[1:255]]
+    picks = sorted({0, 255, 1 + int(np.argmin(sizes)), 1 + int(np.argmax(sizes))})
+    for q in picks:
+        r = probs[q].rounded(np.float32)
+        ref = O.step(r.net, r.pde, r.W, r.x_int, r.x_bc, r.g_bc)
+        lab = f"batched c5 inst{q} ({r.n_int}+{r.n_bc}, nu {r.pde.nu:.2e})"
+        check(f"{lab} loss", relerr(plan.loss[q].cpu().numpy(), ref["loss"]), 1e-5)
+        for l, g in enumerate(plan.layer_grads(q, r.net)):
+            check(f"{lab} gW{l}", relerr(g.double().cpu().numpy(), ref["gW"][l]), 1e-5)
+    plan.close()
 
 
 def test_batched_replays_are_identical_and_follow_weight_updates():

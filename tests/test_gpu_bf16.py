@@ -2,55 +2,79 @@
 with the FP64 oracle.
 
 Jets, bars and accumulation stay FP32; each basis-by-W product (and each
-feature-by-bar product of the weight gradient) is taken as S BF16 products.
-Gate (normwise relative error against the exact oracle on the same FP32
-inputs): max(2e-2, 3 x floor), the floor being the error of the oracle's
-BF16 rounding model -- features and bars split into S BF16 pieces, weights
-rounded to BF16 -- against the exact oracle: what BF16 storage alone costs
-on that network. S = 3 (a_hi b_hi + a_lo b_hi + a_hi b_lo) keeps about 16
-mantissa bits per product and is in addition held to the FP32 gates.
+feature-by-bar product of the weight gradient) is taken as S BF16 products
+(S = 1: a_hi b_hi; S = 2: + a_lo b_hi; S = 3: + a_hi b_lo). The caller passes
+FP32 master weights. With S <= 2 only the high BF16 piece of a weight enters
+any product, so those kernels multiply the weights rounded to BF16; with
+S = 3 the low piece enters as well.
+
+Gate: the literal 2e-2 (normwise relative error), against the oracle fed
+- the FP32 master weights for S = 3,
+- the BF16-rounded weights for S <= 2, the weights those kernels multiply
+  (the error against the FP32 master weights is printed as well).
+Where even that reading cannot meet 2e-2 -- one BF16 piece per feature (S = 1)
+on the deep [2,128,128,128,1] network, whose error against the exact oracle
+is O(1) for any implementation that rounds features to BF16 -- the error is
+printed, not gated, and the step is gated against the oracle's BF16 rounding
+model instead (the same BF16 pieces with FP64 sums), which a wrong row,
+channel or operand would miss by O(1).
 """
 import numpy as np
 import pytest
 
 import oracle as O
-from conftest import relerr
-from gpu_util import SLOTS_OF_MASK, bf16_round, gpu_step, oracle_step, to_dev
+from conftest import check, relerr
+from gpu_util import SLOTS_OF_MASK, bf16_round, gpu_step, to_dev
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-2
-FLOOR_FACTOR = 3.0
-
-
-def bf16_floor_step(pr, S, with_model=False):
-    """Exact oracle step and the relative errors of its BF16 rounding model
-    (weights rounded to BF16) for the loss and each weight gradient; with
-    with_model also the model's step itself."""
-    q = pr.rounded(np.float32)
-    ref = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
-    Wb = [bf16_round(w) for w in q.W]
-    with O.rounding("bf16", min(S, 2)):
-        rnd = O.step(q.net, q.pde, Wb, q.x_int, q.x_bc, q.g_bc)
-    out = ref, relerr(rnd["loss"], ref["loss"]), [relerr(a, b) for a, b in zip(rnd["gW"], ref["gW"])]
-    return out + (rnd,) if with_model else out
-
 
 # Against the rounding model itself (the same BF16 products, FP64 sums) the
 # step is held much closer than against the exact oracle: what is left is
 # FP32 summation order and the FP32 evaluation of each feature before it is
-# rounded, which can move a BF16 rounding by one unit. Measured: 3e-5 .. 4e-3
-# (c2, c3, c4 networks); a wrong row, channel or operand would be O(1).
+# rounded, which can move a BF16 rounding by one unit. A wrong row, channel
+# or operand would be O(1).
 MODEL_TOL = 1e-2
 MODEL_FACTOR = 0.1
 
 
-def check_against_model(loss, gW, rnd, floors_loss, floors_gW):
-    assert relerr(loss, rnd["loss"]) <= max(MODEL_TOL, MODEL_FACTOR * floors_loss)
-    for l, (a, b) in enumerate(zip(gW, rnd["gW"])):
-        assert relerr(a, b) <= max(MODEL_TOL, MODEL_FACTOR * floors_gW[l]), (l, relerr(a, b), floors_gW[l])
+def reading(S):
+    return "f32" if S == 3 else "bf16"
+
+
+def oracle_steps(pr, S):
+    """(oracle on the stated weight reading, oracle on the FP32 master
+    weights, BF16 rounding model or None for S = 3)."""
+    q = pr.rounded(np.float32)
+    Wb = [bf16_round(w) for w in q.W]
+    master = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
+    ref = master if S == 3 else O.step(q.net, q.pde, Wb, q.x_int, q.x_bc, q.g_bc)
+    rnd = None
+    if S <= 2:
+        with O.rounding("bf16", S):
+            rnd = O.step(q.net, q.pde, Wb, q.x_int, q.x_bc, q.g_bc)
+    return ref, master, rnd
+
+
+def check_bf16_step(label, loss, gW, S, ref, master, rnd, gate_exact=True):
+    lab = f"{label} S{S} W={reading(S)}"
+    errs = [relerr(loss, ref["loss"])] + [relerr(a, b) for a, b in zip(gW, ref["gW"])]
+    names = ["loss"] + [f"gW{l}" for l in range(len(gW))]
+    for nm, e in zip(names, errs):
+        if gate_exact:
+            check(f"{lab} {nm}", e, TOL)
+        else:
+            print(f"[parity] {lab} {nm}: err {e:.3e} (reported, not gated)", flush=True)
+    if S <= 2:
+        for l, (a, b) in enumerate(zip(gW, master["gW"])):
+            print(f"[parity] {label} S{S} W=f32 master gW{l}: err {relerr(a, b):.3e} (reported)", flush=True)
+        fl = relerr(rnd["loss"], ref["loss"])
+        check(f"{lab} loss vs model", relerr(loss, rnd["loss"]), MODEL_TOL, fl, MODEL_FACTOR)
+        for l, (a, b, c) in enumerate(zip(gW, rnd["gW"], ref["gW"])):
+            check(f"{lab} gW{l} vs model", relerr(a, b), MODEL_TOL, relerr(b, c), MODEL_FACTOR)
 
 
 @pytest.mark.parametrize("S", [1, 2, 3])
@@ -62,15 +86,12 @@ def test_forward_jets_bf16_burgers_c2_net(S):
     W = [to_dev(w, "f32") for w in pr.W]
     ws = H.alloc_workspace(H.workspace_bytes(nd, pd, pr.n_int, 0))
     jets = H.forward_jets(nd, W, to_dev(pr.x_int, "f32"), H.MASK_BURGERS, ws).double().cpu().numpy()
-    ref = O.forward(q.net, q.W, q.x_int)
-    with O.rounding("bf16", min(S, 2)):
-        rnd = O.forward(q.net, [bf16_round(w) for w in q.W], q.x_int)
+    Wr = q.W if S == 3 else [bf16_round(w) for w in q.W]
+    ref = O.forward(q.net, Wr, q.x_int)
     for c, slot in enumerate(SLOTS_OF_MASK[H.MASK_BURGERS]):
-        floor = relerr(rnd[slot], ref[slot])
-        err = relerr(jets[c], ref[slot])
-        assert err <= max(TOL, FLOOR_FACTOR * floor), (S, c, err, floor)
+        check(f"c2 bf16 S{S} W={reading(S)} jet{slot}", relerr(jets[c], ref[slot]), TOL)
         if S == 3:
-            assert err <= 1e-4, (c, err)
+            check(f"c2 bf16 S3 jet{slot} (FP32 reading)", relerr(jets[c], ref[slot]), 1e-4)
 
 
 @pytest.mark.parametrize("S", [1, 2, 3])
@@ -78,50 +99,41 @@ def test_forward_jets_bf16_burgers_c2_net(S):
 def test_step_bf16(name, S):
     pr = WL.make_problem(WL.WORKLOADS[name], n_int=4096 + 37, n_bc=256)
     loss, gW, ws = gpu_step(pr, "bf16", S)
-    ref, fl, fg, rnd = bf16_floor_step(pr, S, with_model=True)
     assert H.read_status(ws) == 0
-    assert relerr(loss, ref["loss"]) <= max(TOL, FLOOR_FACTOR * fl), (loss, ref["loss"], fl)
-    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
-        assert relerr(a, b) <= max(TOL, FLOOR_FACTOR * fg[l]), (l, relerr(a, b), fg[l])
-    if S <= 2:
-        check_against_model(loss, gW, rnd, fl, fg)
+    ref, master, rnd = oracle_steps(pr, S)
+    check_bf16_step(f"{name} bf16", loss, gW, S, ref, master, rnd)
     if S == 3 and name == "burgers_c2":
-        f32 = oracle_step(pr, "f32")
-        assert relerr(loss, f32["loss"]) <= 1e-4
+        check("burgers_c2 bf16 S3 loss (FP32 reading)", relerr(loss, master["loss"]), 1e-4)
 
 
-def test_step_bf16_s2_burgers_c4_net_bf16_weights():
-    """The [2,128,128,128,1], G = 20 network with weights already on the
-    BF16 grid: the oracle gets exactly the weights the matrix cores use."""
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_step_bf16_burgers_c4_net(S):
+    """The [2,128,128,128,1], G = 20 network with FP32 master weights, as the
+    step, the trainer and the benchmark pass them: S = 3 against the oracle on
+    the master weights, S = 2 against the oracle on the BF16-rounded weights,
+    both at the literal 2e-2; S = 1 against the rounding model (its error
+    against the exact oracle is printed)."""
     pr = WL.make_problem(WL.WORKLOADS["burgers_c4"], n_int=2048 + 11, n_bc=128)
-    pr = WL.Problem(pr.net, pr.pde, [bf16_round(w) for w in pr.W], pr.x_int, pr.x_bc, pr.g_bc)
-    loss, gW, _ = gpu_step(pr, "bf16", 2)
-    ref, fl, fg, rnd = bf16_floor_step(pr, 2, with_model=True)
-    assert relerr(loss, ref["loss"]) <= max(TOL, FLOOR_FACTOR * fl), (relerr(loss, ref["loss"]), fl)
-    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
-        assert relerr(a, b) <= max(TOL, FLOOR_FACTOR * fg[l]), (l, relerr(a, b), fg[l])
-    # the literal BF16 tolerance, which this network meets with weights on the BF16 grid
-    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
-        assert relerr(a, b) <= TOL, (l, relerr(a, b))
-    check_against_model(loss, gW, rnd, fl, fg)
+    loss, gW, ws = gpu_step(pr, "bf16", S)
+    assert H.read_status(ws) == 0
+    ref, master, rnd = oracle_steps(pr, S)
+    check_bf16_step("burgers_c4 bf16", loss, gW, S, ref, master, rnd, gate_exact=(S >= 2))
 
 
 @pytest.mark.parametrize("widths,G,S", [
     ((2, 64, 32, 64, 1), 10, 2),    # dense hidden layers with 32 and 64 outputs, 64 and 32 inputs
     ((2, 32, 32, 1), 25, 2),        # 28 basis functions per input: hidden layer on the block-sparse BF16 kernels
     ((2, 32, 32, 1), 4, 1),         # 7 basis functions: 8 padded rows per input
+    ((2, 32, 32, 1), 4, 3),
 ])
 def test_step_bf16_ragged_shapes(widths, G, S):
     wl = WL.WORKLOADS["burgers_c2"]
     wl = WL.Workload("ragged", WL.Net(widths, G=G), wl.pde, 777, 12, "f32", wl.seed + 17)
     pr = WL.make_problem(wl)
     loss, gW, ws = gpu_step(pr, "bf16", S)
-    ref, fl, fg, rnd = bf16_floor_step(pr, S, with_model=True)
     assert H.read_status(ws) == 0
-    assert relerr(loss, ref["loss"]) <= max(TOL, FLOOR_FACTOR * fl), (relerr(loss, ref["loss"]), fl)
-    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
-        assert relerr(a, b) <= max(TOL, FLOOR_FACTOR * fg[l]), (l, relerr(a, b), fg[l])
-    check_against_model(loss, gW, rnd, fl, fg)
+    ref, master, rnd = oracle_steps(pr, S)
+    check_bf16_step(f"ragged {widths} G{G} bf16", loss, gW, S, ref, master, rnd)
 
 
 def test_bf16_step_is_deterministic():

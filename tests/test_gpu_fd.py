@@ -1,5 +1,5 @@
 """Finite-difference check of the HIP path's FP64 gradient on the Poisson
-network [2,64,64,64,1], G = 16 (Sec. 3.1's problem at the larger network).
+network [2,64,64,64,1], G = 16 (Sec. 4.1's problem at the larger network).
 
 The loss L(W) = alpha L_pde + L_bc is evaluated by the same HIP step, in FP64,
 at W +- h V; central differences with h = 1e-4 are compared with the

@@ -10,14 +10,15 @@ The first and last points are always in the sample.
 
 Gates are those of the small-size tests, taken over the sample (normwise
 per channel):
-- FP32: max(1e-5, 10 x the oracle's FP32 rounding floor);
-- BF16: max(2e-2, 3 x the floor of the oracle's BF16 rounding model).
+- FP32: max(1e-5, 3 x the oracle's FP32 rounding floor);
+- BF16 (S = 2): the literal 2e-2 against the oracle on the BF16-rounded
+  weights that the S = 2 kernels multiply.
 """
 import numpy as np
 import pytest
 
 import oracle as O
-from conftest import relerr
+from conftest import check, relerr
 from gpu_util import SLOTS_OF_MASK, bf16_round, to_dev
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
@@ -26,7 +27,7 @@ pytestmark = pytest.mark.gpu
 
 SAMPLE = 64
 TOL = {"f32": 1e-5, "bf16": 2e-2}
-FLOOR_FACTOR = {"f32": 10.0, "bf16": 3.0}
+FLOOR_FACTOR = 3.0
 
 
 def sample_points(n, seed):
@@ -50,17 +51,18 @@ def test_full_size_forward_jets_at_sampled_points(name, dtype):
     got = jets[:, idx].double().cpu().numpy()
     del jets, ws
     xs = q.x_int[idx]
-    ref = O.forward(q.net, q.W, xs)
     if dtype == "f32":
+        ref = O.forward(q.net, q.W, xs)
         with O.rounding("f32"):
             rnd = O.forward(q.net, q.W, xs)
     else:
-        with O.rounding("bf16", 2):
-            rnd = O.forward(q.net, [bf16_round(w) for w in q.W], xs)
+        ref = O.forward(q.net, [bf16_round(w) for w in q.W], xs)
     for c, slot in enumerate(SLOTS_OF_MASK[mask]):
-        floor = relerr(rnd[slot], ref[slot])
         err = relerr(got[c], ref[slot])
-        assert err <= max(TOL[dtype], FLOOR_FACTOR[dtype] * floor), (name, dtype, c, err, floor)
+        if dtype == "f32":
+            check(f"{name} full sampled f32 jet{slot}", err, TOL["f32"], relerr(rnd[slot], ref[slot]), FLOOR_FACTOR)
+        else:
+            check(f"{name} full sampled bf16 S2 W=bf16 jet{slot}", err, TOL["bf16"])
 
 
 def _step(pr, dtype, x_int, x_bc, g_bc):

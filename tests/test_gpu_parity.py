@@ -1,52 +1,73 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (normwise relative error ||gpu - oracle|| / ||oracle||):
-  FP64 path: 1e-10.  FP32 path: 1e-5 where the network's conditioning allows
-  it. Where it does not, the end-to-end gate is FLOOR_FACTOR x the error of
-  the oracle's FP32 rounding model (one rounding per basis feature, an FP32
-  fused multiply-add chain for every contraction, FP32 storage of every jet):
-  the floor any FP32 implementation meets on that network. The kernels
-  evaluate each feature with about ten dependent FP32 operations where the
-  model rounds once, so their error may sit a few times above the floor. Every layer is
-  in addition checked teacher-forced (the oracle fed the GPU's own layer
-  inputs) at the plain 1e-5.
+Tolerances, normwise relative error ||gpu - oracle|| / ||oracle|| (and, for
+jets and residuals, also the max-scaled element-wise error
+max|gpu - oracle| / max|oracle|):
+- FP64 path: 1e-10.
+- FP32 path: the literal 1e-5 on the networks of the Burgers workloads
+  [2,32,32,1] (single and batched) and of the paper's instances, and for every
+  layer checked teacher-forced (the oracle fed the GPU's own layer inputs).
+  On the deeper [2,64,64,64,1] and [2,128,128,128,1] networks and the other
+  test networks, the floor that FP32 storage alone costs exceeds 1e-5 for any
+  implementation; there the gate is max(1e-5, 3 x floor), the floor being the
+  error of the oracle's FP32 rounding model (one rounding per basis feature,
+  an FP32 fused multiply-add chain for every contraction, FP32 storage of
+  every jet and bar) on the same inputs.
+Every check prints the error it reached, its gate and the floor.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
-from conftest import relerr
-from gpu_util import (NP_DTYPE, expand, gpu_forward, gpu_step, oracle_step, saved_blocks, to_dev)
+from conftest import check, maxerr, relerr
+from gpu_util import (NP_DTYPE, SLOTS_OF_MASK, expand, gpu_forward, gpu_step, oracle_step, saved_blocks,
+                      to_dev)
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
-FLOOR_FACTOR = 10.0
+FLOOR_FACTOR = 3.0
 
 
-def fp32_floor(pr: WL.Problem, x, mask):
-    """Error of the oracle's FP32 rounding model against the exact oracle:
-    the floor any FP32 implementation meets on this network."""
-    q = pr.rounded(np.float32)
-    ref = O.forward(q.net, q.W, x)
-    with O.rounding("f32"):
-        rnd = O.forward(q.net, q.W, x)
-    slots = __import__("gpu_util").SLOTS_OF_MASK[mask]
-    return max(relerr(rnd[s], ref[s]) for s in slots)
-
-
-def fp32_step_gates(pr: WL.Problem):
-    """Gates for a whole FP32 step: max(1e-5, FLOOR_FACTOR x the error of the
-    oracle's FP32 rounding model) for the loss and for each weight gradient."""
+def oracle_pair_f32(pr: WL.Problem):
+    """The exact oracle step and its FP32 rounding model on the FP32 inputs."""
     q = pr.rounded(np.float32)
     ref = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
     with O.rounding("f32"):
         rnd = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
-    gate = lambda a, b: max(TOL["f32"], FLOOR_FACTOR * relerr(a, b))
-    return ref, gate(rnd["loss"], ref["loss"]), [gate(a, b) for a, b in zip(rnd["gW"], ref["gW"])]
+    return ref, rnd
+
+
+def check_step_f32(label, pr, loss, gW, literal, pair=None):
+    """Loss and every weight gradient of an FP32 step against the oracle:
+    literal 1e-5, or max(1e-5, 3 x floor)."""
+    ref, rnd = pair or oracle_pair_f32(pr)
+    check(f"{label} loss", relerr(loss, ref["loss"]), TOL["f32"], relerr(rnd["loss"], ref["loss"]),
+          FLOOR_FACTOR, literal)
+    for l, (a, b, c) in enumerate(zip(gW, ref["gW"], rnd["gW"])):
+        if np.linalg.norm(b) == 0:
+            assert np.max(np.abs(a)) == 0.0, (label, l)
+            continue
+        check(f"{label} gW{l}", relerr(a, b), TOL["f32"], relerr(c, b), FLOOR_FACTOR, literal)
+    return ref
+
+
+def check_f64(label, loss, gW, ref):
+    check(f"{label} loss", relerr(loss, ref["loss"]), TOL["f64"])
+    for l, (a, b) in enumerate(zip(gW, ref["gW"])):
+        check(f"{label} gW{l}", relerr(a, b), TOL["f64"])
+
+
+def check_jets(label, jets, ref, rnd, mask, tol, literal):
+    """Each channel normwise and max-scaled element-wise."""
+    for c, s in enumerate(SLOTS_OF_MASK[mask]):
+        fl_n = relerr(rnd[s], ref[s]) if rnd is not None else None
+        fl_m = maxerr(rnd[s], ref[s]) if rnd is not None else None
+        check(f"{label} jet{s} norm", relerr(jets[c], ref[s]), tol, fl_n, FLOOR_FACTOR, literal)
+        check(f"{label} jet{s} max", maxerr(jets[c], ref[s]), tol, fl_m, FLOOR_FACTOR, literal)
 
 
 # ---------------------------------------------------------------------------
@@ -55,18 +76,14 @@ def fp32_step_gates(pr: WL.Problem):
 def test_step_poisson_c1_f64():
     pr = WL.make_problem(WL.WORKLOADS["poisson_c1"])
     loss, gW, _ = gpu_step(pr, "f64")
-    ref = oracle_step(pr, "f64")
-    assert relerr(loss, ref["loss"]) < 1e-10
-    for a, b in zip(gW, ref["gW"]):
-        assert relerr(a, b) < 1e-10
+    check_f64("c1 f64", loss, gW, oracle_step(pr, "f64"))
 
 
 def test_forward_jets_poisson_c1_f64():
     pr = WL.make_problem(WL.WORKLOADS["poisson_c1"])
     jets, *_ = gpu_forward(pr, "f64", pr.x_int, H.MASK_POISSON)
     ref = O.forward(pr.net, pr.W, pr.x_int)
-    for c in range(5):
-        assert relerr(jets[c], ref[c]) < 1e-10, c
+    check_jets("c1 f64", jets, ref, None, H.MASK_POISSON, TOL["f64"], True)
 
 
 @pytest.mark.parametrize("name", ["burgers_c2", "poisson_c3", "burgers_c4"])
@@ -74,10 +91,7 @@ def test_step_f64_at_each_network_shape(name):
     wl = WL.WORKLOADS[name]
     pr = WL.make_problem(wl, n_int=1000, n_bc=64)
     loss, gW, _ = gpu_step(pr, "f64")
-    ref = oracle_step(pr, "f64")
-    assert relerr(loss, ref["loss"]) < 1e-10
-    for a, b in zip(gW, ref["gW"]):
-        assert relerr(a, b) < 1e-10
+    check_f64(f"{name} f64", loss, gW, oracle_step(pr, "f64"))
 
 
 @pytest.mark.parametrize("k,m", [(3, 2), (3, 3), (3, 5), (2, 4), (1, 3), (0, 2)])
@@ -85,9 +99,9 @@ def test_step_f64_at_each_network_shape(name):
 def test_step_other_orders(k, m, dtype):
     """Other support widths k and HR orders m (Eq. 2; m = 2 is the
     ReLU-KAN basis of Eq. 1) run on the generic kernels; the FP64 step meets
-    1e-10 against the oracle, the FP32 step its rounding-model gate. With
+    1e-10 against the oracle, the FP32 step max(1e-5, 3 x floor). With
     m = 2 the second derivative of a bump jumps at its support ends (the
-    smoothness argument of Sec. 2.3); random points fall on no knot, so the
+    smoothness argument of Sec. 3); random points fall on no knot, so the
     comparison stays well defined."""
     net = WL.Net((2, 6, 5, 1), G=6, k=k, m=m)
     wl = WL.Workload("orders", net, WL.Pde(WL.BURGERS1D, WL.NU_BURGERS), 700, 48, dtype,
@@ -96,15 +110,9 @@ def test_step_other_orders(k, m, dtype):
     loss, gW, ws = gpu_step(pr, dtype)
     assert H.read_status(ws) == 0
     if dtype == "f64":
-        ref = oracle_step(pr, "f64")
-        assert relerr(loss, ref["loss"]) < 1e-10
-        for a, b in zip(gW, ref["gW"]):
-            assert relerr(a, b) < 1e-10
+        check_f64(f"k{k} m{m} f64", loss, gW, oracle_step(pr, "f64"))
     else:
-        ref, gl, gg = fp32_step_gates(pr)
-        assert relerr(loss, ref["loss"]) < gl
-        for a, b, gt in zip(gW, ref["gW"], gg):
-            assert relerr(a, b) < gt
+        check_step_f32(f"k{k} m{m} f32", pr, loss, gW, literal=False)
 
 
 # The deepest and widest networks the interface takes: 8 layers, one of them
@@ -121,20 +129,14 @@ def test_step_max_layers_and_width(dtype, n_int):
     loss, gW, ws = gpu_step(pr, dtype)
     assert H.read_status(ws) == 0
     if dtype == "f64":
-        ref = oracle_step(pr, "f64")
-        assert relerr(loss, ref["loss"]) < 1e-10
-        for a, b in zip(gW, ref["gW"]):
-            assert relerr(a, b) < 1e-10
+        check_f64(f"deep {n_int} f64", loss, gW, oracle_step(pr, "f64"))
     else:
-        ref, gl, gg = fp32_step_gates(pr)
-        assert relerr(loss, ref["loss"]) < gl
-        for a, b, gt in zip(gW, ref["gW"], gg):
-            assert relerr(a, b) < gt
+        check_step_f32(f"deep {n_int} f32", pr, loss, gW, literal=False)
 
 
 def special_points():
     """Coordinates on the knots of the c2 grid (G = 10 on [-1, 1], h = 0.2,
-    supports extended by k h beyond each end: Sec. 2.2), one FP32 unit on
+    supports extended by k h beyond each end: Sec. 2.1-2.2), one FP32 unit on
     either side of them, on the grid ends and far outside it, paired in
     every combination of a short list."""
     h = 0.2
@@ -149,9 +151,10 @@ def special_points():
 
 
 # The window and support tests of every kernel at the points where they
-# switch: inputs on knots (the basis is C^2, Eq. 2 with m = 4, so either
+# switch: inputs on knots (the basis is C^3, Eq. 2 with m = 4, so either
 # window gives the same values), on the ends of the extended supports and
-# far outside them (all-zero basis).
+# far outside them (all-zero basis). The network is the Burgers [2,32,32,1]
+# one, so FP32 is held to the literal 1e-5, element-wise as well.
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_step_at_knots_and_outside_the_grid(dtype):
     base = WL.make_problem(WL.WORKLOADS["burgers_c2"], n_int=8, n_bc=8)
@@ -165,21 +168,14 @@ def test_step_at_knots_and_outside_the_grid(dtype):
     ref = O.forward(q.net, q.W, q.x_int)
     loss, gW, ws = gpu_step(pr, dtype)
     assert H.read_status(ws) == 0
-    sref = oracle_step(pr, dtype)
     if dtype == "f64":
-        for c, sl in enumerate(__import__("gpu_util").SLOTS_OF_MASK[mask]):
-            assert relerr(jets[c], ref[sl]) < 1e-10, c
-        assert relerr(loss, sref["loss"]) < 1e-10
-        for a, b in zip(gW, sref["gW"]):
-            assert relerr(a, b) < 1e-10
+        check_jets("knots f64", jets, ref, None, mask, TOL["f64"], True)
+        check_f64("knots f64", loss, gW, oracle_step(pr, "f64"))
     else:
-        gate = max(TOL["f32"], FLOOR_FACTOR * fp32_floor(pr, q.x_int, mask))
-        for c, sl in enumerate(__import__("gpu_util").SLOTS_OF_MASK[mask]):
-            assert relerr(jets[c], ref[sl]) < gate, (c, relerr(jets[c], ref[sl]), gate)
-        _, gl, gg = fp32_step_gates(pr)
-        assert relerr(loss, sref["loss"]) < gl
-        for a, b, gt in zip(gW, sref["gW"], gg):
-            assert relerr(a, b) < gt
+        with O.rounding("f32"):
+            rnd = O.forward(q.net, q.W, q.x_int)
+        check_jets("knots f32", jets, ref, rnd, mask, TOL["f32"], True)
+        check_step_f32("knots f32", pr, loss, gW, literal=True)
 
 
 # ---------------------------------------------------------------------------
@@ -195,23 +191,26 @@ def test_step_burgers_c2_shape_f32_sizes(n_int, n_bc):
     wl = WL.WORKLOADS["burgers_c2"]
     pr = WL.make_problem(wl, n_int=n_int, n_bc=n_bc)
     loss, gW, _ = gpu_step(pr, "f32")
-    ref, gl, gg = fp32_step_gates(pr)
-    assert relerr(loss, ref["loss"]) < gl
-    for a, b, gt in zip(gW, ref["gW"], gg):
-        if np.linalg.norm(b) > 0:
-            assert relerr(a, b) < gt
-        else:
-            assert np.max(np.abs(a)) == 0.0
+    check_step_f32(f"c2 {n_int}+{n_bc} f32", pr, loss, gW, literal=True)
 
 
 @pytest.mark.slow
 def test_step_burgers_c2_full_f32():
     pr = WL.make_problem(WL.WORKLOADS["burgers_c2"])
     loss, gW, _ = gpu_step(pr, "f32")
-    ref = oracle_step(pr, "f32")
-    assert relerr(loss, ref["loss"]) < TOL["f32"]
-    for a, b in zip(gW, ref["gW"]):
-        assert relerr(a, b) < TOL["f32"]
+    check_step_f32("c2 full f32", pr, loss, gW, literal=True)
+
+
+@pytest.mark.parametrize("name", ["poisson_c3", "burgers_c4"])
+def test_step_deep_network_f32(name):
+    """A small FP32 step on the deeper networks: every FP32 kernel of their
+    hidden layers (the 64- and 128-output weight gradients split over two
+    output blocks, the four-point gradient loop of the 128-output layers,
+    the 32-quad input bars) against the oracle, end to end."""
+    pr = WL.make_problem(WL.WORKLOADS[name], n_int=1500 + 7, n_bc=96)
+    loss, gW, ws = gpu_step(pr, "f32")
+    assert H.read_status(ws) == 0
+    check_step_f32(f"{name} 1507 f32", pr, loss, gW, literal=False)
 
 
 @pytest.mark.parametrize("name,mask", [("burgers_c2", H.MASK_BURGERS), ("poisson_c3", H.MASK_POISSON),
@@ -227,11 +226,11 @@ def test_forward_layers_teacher_forced_f32(name, mask):
     blocks = saved_blocks(pr, sv, "f32", C, n)
     ins = [O.input_jets(x)] + [expand(b, mask) for b in blocks]
     outs = [expand(b, mask) for b in blocks] + [expand(jets.reshape(C, 1, n), mask)]
-    slots = __import__("gpu_util").SLOTS_OF_MASK[mask]
     for l, W in enumerate(q.W):
         ref = O.layer_forward(q.net, l, W, ins[l])
-        for s in slots:
-            assert relerr(outs[l][s], ref[s]) < TOL["f32"], (l, s)
+        for s in SLOTS_OF_MASK[mask]:
+            check(f"{name} tf fwd l{l} slot{s} norm", relerr(outs[l][s], ref[s]), TOL["f32"])
+            check(f"{name} tf fwd l{l} slot{s} max", maxerr(outs[l][s], ref[s]), TOL["f32"])
 
 
 @pytest.mark.parametrize("name,mask", [("burgers_c2", H.MASK_BURGERS), ("poisson_c3", H.MASK_POISSON),
@@ -242,16 +241,41 @@ def test_forward_end_to_end_f32(name, mask):
     q = pr.rounded(np.float32)
     jets, *_ = gpu_forward(pr, "f32", q.x_int, mask)
     ref = O.forward(q.net, q.W, q.x_int)
-    floor = fp32_floor(pr, q.x_int, mask)
-    gate = max(TOL["f32"], FLOOR_FACTOR * floor)
-    for c, s in enumerate(__import__("gpu_util").SLOTS_OF_MASK[mask]):
-        assert relerr(jets[c], ref[s]) < gate, (c, relerr(jets[c], ref[s]), floor)
+    with O.rounding("f32"):
+        rnd = O.forward(q.net, q.W, q.x_int)
+    check_jets(f"{name} e2e f32", jets, ref, rnd, mask, TOL["f32"], literal=(name == "burgers_c2"))
 
 
 @pytest.mark.parametrize("name,mask", [("burgers_c2", H.MASK_BURGERS), ("poisson_c3", H.MASK_POISSON)])
+def test_residual_elementwise_f32(name, mask):
+    """Forward jets and the residual call at 4,099 points: r against the
+    oracle's residual normwise and element-wise (max-scaled)."""
+    pr = WL.make_problem(WL.WORKLOADS[name], n_int=4096 + 3, n_bc=64)
+    q = pr.rounded(np.float32)
+    nd = H.net_desc(pr.net, "f32")
+    pd = H.pde_desc(pr.pde)
+    W = [to_dev(w, "f32") for w in pr.W]
+    ws = H.alloc_workspace(H.workspace_bytes(nd, pd, q.n_int, q.n_bc))
+    xi, xb, g = to_dev(q.x_int, "f32"), to_dev(q.x_bc, "f32"), to_dev(q.g_bc, "f32")
+    jets = H.forward_jets(nd, W, xi, mask, ws)
+    ub = H.forward_jets(nd, W, xb, H.MASK_VALUE, ws)
+    r = torch.empty(q.n_int, dtype=torch.float32, device="cuda")
+    H.residual(pd, H.F32, jets, ub[0], xi, g, ws, r_out=r)
+    torch.cuda.synchronize()
+    ref, rnd = oracle_pair_f32(pr)
+    literal = name == "burgers_c2"
+    got = r.double().cpu().numpy()
+    check(f"{name} r norm", relerr(got, ref["r"]), TOL["f32"], relerr(rnd["r"], ref["r"]), FLOOR_FACTOR, literal)
+    check(f"{name} r max", maxerr(got, ref["r"]), TOL["f32"], maxerr(rnd["r"], ref["r"]), FLOOR_FACTOR, literal)
+
+
+@pytest.mark.parametrize("name,mask", [("burgers_c2", H.MASK_BURGERS), ("poisson_c3", H.MASK_POISSON),
+                                       ("burgers_c4", H.MASK_BURGERS)])
 def test_backward_teacher_forced_f32(name, mask):
     """GPU weight gradient for given seeds vs the oracle reverse pass fed the
-    GPU's saved forward jets."""
+    GPU's saved forward jets. Layer l's bars come from the oracle's chain, so
+    the layers below the last are compared end to end over the reverse pass
+    but teacher-forced on the forward jets."""
     wl = WL.WORKLOADS[name]
     pr = WL.make_problem(wl, n_int=1500, n_bc=4)
     q = pr.rounded(np.float32)
@@ -266,13 +290,13 @@ def test_backward_teacher_forced_f32(name, mask):
     ybar = expand(seed.astype(np.float64).reshape(C, 1, n), mask)
     for l in range(len(q.W) - 1, -1, -1):
         zbar, ref = O.layer_backward(q.net, l, q.W[l], ins[l], ybar)
-        assert relerr(gW[l].double().cpu().numpy(), ref) < TOL["f32"], l
+        check(f"{name} tf bwd gW{l}", relerr(gW[l].double().cpu().numpy(), ref), TOL["f32"])
         ybar = zbar
         if l > 0:
             # the GPU's bars are internal; keep the oracle's chain but drop the
             # channels the mask does not carry
             keep = np.zeros_like(ybar)
-            keep[__import__("gpu_util").SLOTS_OF_MASK[mask]] = ybar[__import__("gpu_util").SLOTS_OF_MASK[mask]]
+            keep[SLOTS_OF_MASK[mask]] = ybar[SLOTS_OF_MASK[mask]]
             ybar = keep
 
 
