@@ -205,6 +205,27 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
                const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
                size_t ws_bytes, hipStream_t stream);
 
+/* hrkan_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same step, with the workspace taken from a static device array of the
+ * library, HRKAN_STATIC_SCRATCH_BYTES (64 MiB) per GPU, which each GPU the
+ * library runs on holds until the process ends. The caller still passes
+ * weights, points, loss_out and gW_out (same meaning and layouts as
+ * hrkan_step). The call allocates nothing: no hipMalloc, no stream or event
+ * (both point sets run on `stream`). Its first call on a device looks up that
+ * device's array and clears its status word on `stream`.
+ * Errors: HRKAN_ERR_WORKSPACE (nothing enqueued) when the step needs more
+ * workspace than the array holds (hrkan_workspace_bytes for the same
+ * counts; e.g. the [2,32,32,1] Burgers network fits up to about 14,000
+ * interior points); HRKAN_ERR_UNSUPPORTED while per-launch profiling is on;
+ * otherwise those of hrkan_step. All calls on one GPU share its array, which
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+#define HRKAN_STATIC_SCRATCH_BYTES (64u << 20)
+int hrkan_step_static(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
+                      const hrkan_points *pts, double *loss_out, void *const *gW_out,
+                      hipStream_t stream);
+
 /* Adam update of every layer's weights in place, for training with the
  * optimiser the paper uses (Sec. 4.1, 4.2: Adam, 3000 epochs), with the
  * published update of Kingma and Ba: with t = *step_dev + 1,

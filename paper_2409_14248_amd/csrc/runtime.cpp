@@ -742,6 +742,17 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
                const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
                size_t ws_bytes, hipStream_t stream)
 {
+    return step_impl(net, pde, W, pts, loss_out, gW_out, ws, ws_bytes, stream, true);
+}
+
+}  // extern "C"
+
+namespace hrk {
+
+int step_impl(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
+              const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
+              size_t ws_bytes, hipStream_t stream, bool allow_fork)
+{
     NetInfo ni;
     TRY(check_net(net, &ni));
     TRY(check_pde(pde));
@@ -802,7 +813,7 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
         // residual, joined after each pass. The interior set's launches are
         // enqueued first: it is the longer chain.
         Fork *fk = nullptr;
-        if (overlap_sets(ni, ni_, nb_) && !prof_on()) TRY(get_fork(stream, &fk));
+        if (allow_fork && overlap_sets(ni, ni_, nb_) && !prof_on()) TRY(get_fork(stream, &fk));
         hipStream_t sb = fk ? fk->side : stream;
         // no gradient needs the loss value: the gradient reduction's launch
         // sums it too
@@ -841,6 +852,10 @@ int hrkan_step(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void 
     if (ni.dtype == HRKAN_F64) return run(double{});
     return run(float{});
 }
+
+}  // namespace hrk
+
+extern "C" {
 
 int hrkan_adam(const hrkan_net_desc *net, void *const *W, const void *const *gW, void *const *m,
                void *const *v, int64_t *step_dev, double lr, double beta1, double beta2, double eps,

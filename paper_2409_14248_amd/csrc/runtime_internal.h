@@ -77,6 +77,12 @@ class ProfScope {
 };
 bool prof_on();
 
+// hrkan_step with the workspace ws; allow_fork = false keeps every launch on
+// `stream` (no side stream is created or used).
+int step_impl(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *const *W,
+              const hrkan_points *pts, double *loss_out, void *const *gW_out, void *ws,
+              size_t ws_bytes, hipStream_t stream, bool allow_fork);
+
 
 
 }  // namespace hrk

@@ -39,7 +39,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_PLAN_MISMAT
 EXPORTS = [
     "hrkan_net_init", "hrkan_pde_init", "hrkan_mask_channels", "hrkan_saved_bytes",
     "hrkan_workspace_bytes", "hrkan_forward_jets", "hrkan_residual", "hrkan_backward",
-    "hrkan_step", "hrkan_adam", "hrkan_plan_workspace_bytes", "hrkan_plan_create", "hrkan_plan_execute",
+    "hrkan_step", "hrkan_step_static", "hrkan_adam", "hrkan_plan_workspace_bytes", "hrkan_plan_create", "hrkan_plan_execute",
     "hrkan_plan_config", "hrkan_plan_destroy", "hrkan_read_status", "hrkan_status_string",
     "hrkan_last_error", "hrkan_version", "hrkan_profile_enable", "hrkan_profile_read",
 ]
@@ -109,6 +109,7 @@ def lib():
     L.hrkan_residual.argtypes = [P(PdeDesc), i32, vp, vp, P(Points), vp, vp, vp, vp, vp, sz, vp]
     L.hrkan_backward.argtypes = [P(NetDesc), P(vp), vp, i64, u32, vp, vp, P(vp), i32, vp, sz, vp]
     L.hrkan_step.argtypes = [P(NetDesc), P(PdeDesc), P(vp), P(Points), vp, P(vp), vp, sz, vp]
+    L.hrkan_step_static.argtypes = [P(NetDesc), P(PdeDesc), P(vp), P(Points), vp, P(vp), vp]
     L.hrkan_adam.argtypes = [P(NetDesc), P(vp), P(vp), P(vp), P(vp), vp, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, vp]
     L.hrkan_plan_workspace_bytes.argtypes = [P(NetDesc), i32, P(Points), P(sz)]
@@ -281,6 +282,20 @@ def step(nd: NetDesc, pd: PdeDesc, W: Sequence[torch.Tensor], x_int: torch.Tenso
     pts = Points(x_int.data_ptr(), x_int.shape[0], x_bc.data_ptr(), x_bc.shape[0], g_bc.data_ptr())
     check(lib().hrkan_step(ctypes.byref(nd), ctypes.byref(pd), _ptr_array(W), ctypes.byref(pts),
                            _ptr(loss_out), _ptr_array(gW_out), _ptr(ws), ws.numel(), _stream(stream)))
+    return loss_out, gW_out
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def step_static(nd: NetDesc, pd: PdeDesc, W: Sequence[torch.Tensor], x_int: torch.Tensor,
+                x_bc: torch.Tensor, g_bc: torch.Tensor, loss_out: torch.Tensor,
+                gW_out: List[torch.Tensor], stream=None):
+    """hrkan_step_static: the step with the library's static device workspace
+    (no allocation in the call; the caller passes every output buffer)."""
+    pts = Points(x_int.data_ptr(), x_int.shape[0], x_bc.data_ptr(), x_bc.shape[0], g_bc.data_ptr())
+    check(lib().hrkan_step_static(ctypes.byref(nd), ctypes.byref(pd), _ptr_array(W), ctypes.byref(pts),
+                                  _ptr(loss_out), _ptr_array(gW_out), _stream(stream)))
     return loss_out, gW_out
 
 
