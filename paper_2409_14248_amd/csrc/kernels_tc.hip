@@ -1,0 +1,847 @@
+// kernels_tc.hip -- tile-coherent FP32 matrix-core kernels of one hidden KAN
+// layer for the HR basis with k = 3 supports and order m = 4 (Eq. 2).
+//
+// A wave takes a tile of 16 consecutive points. When the point set is
+// ordered along a space-filling curve, the points of a tile lie close
+// together in the domain, so each of a hidden layer's inputs takes nearby
+// values on them and only a few basis rows are non-zero on the whole tile:
+// the union of the tile's 4-row windows, rows r0_i .. r1_i of input i. The
+// tile's K axis is the concatenation of those rows over the inputs (a few
+// more than the 4 live rows per point and input; rows outside a point's own
+// support give a zero feature), and the contraction runs on the 16x16x4
+// FP32 MFMA with the 16 points as the M axis: the weight row of a K entry is
+// the B operand of all 16 points at once. The kernels are correct for any
+// point order; the order only sets how long the K axis is.
+//
+// The basis and its derivatives are evaluated in FP64 from the offsets of the
+// FP32 input to the support ends, a = z - s_b and be = e_b - z (knots in
+// FP64), and each feature is rounded to FP32 once: on a deep network the
+// error of the first layers' features is amplified by the later ones, and
+// FP32 evaluation (several roundings per feature, and z - s_b taken at the
+// magnitude of the scaled coordinate) would put the step's error well above
+// what FP32 storage of the features alone costs. The first layer (inputs
+// are the coordinates, jets (1, 0) and (0, 1)) runs on the same kernels.
+//
+// MFMA lane layout (16x16x4 FP32, wave of 64): lane l, r16 = l % 16,
+// g = l / 16: A[r16][g], B[g][r16], D[4 g + r][r16] (r = 0..3).
+#include <algorithm>
+
+#include "internal.h"
+#include "kernels_tc.h"
+
+namespace hrk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int TNT = 256;            // threads per block: 4 independent waves
+constexpr int TW = TNT / 64;
+constexpr int TPT = 16;             // points per wave tile
+constexpr int TKJ = 16;             // inputs per chunk
+constexpr int MAXNB = 32;           // basis rows per input (n_b) at most
+
+// Rows of a chunk's K list: up to TKJ * MAXNB entries, padded to 4.
+constexpr int MAXK = TKJ * MAXNB;
+
+template <int O0, int O1>
+struct TcLds {
+    static constexpr int C = 1 + O0 + O1;
+    float z[C][TKJ][TPT];               // the chunk's jets of the tile
+    unsigned short ent[MAXK];           // K entry: input (high byte) and row (low byte)
+    int nent;
+};
+
+// v, v', v'' of bump b at FP32 input z, in FP64 (derivatives in z units:
+// inv_w per order); zero off the open support, a NaN input carried.
+__device__ __forceinline__ void bump3d(double2 kn, float z, double inv_w, double &v0, double &v1, double &v2)
+{
+    const double zd = (double)z;
+    const double a = (zd - kn.x) * inv_w, be = (kn.y - zd) * inv_w;
+    const bool in = !(a <= 0.0) && !(be <= 0.0);
+    const double t = a * be, d = be - a, t2 = t * t;
+    v0 = in ? t2 * t2 : 0.0;
+    v1 = in ? (4.0 * inv_w) * (t2 * t) * d : 0.0;
+    v2 = in ? (4.0 * inv_w * inv_w) * t2 * (3.0 * d * d - 2.0 * t) : 0.0;
+}
+
+// Feature of channel c from the bump and the point's jets of the input,
+// computed in FP64 and rounded once.
+template <int O0, int O1>
+__device__ __forceinline__ float feature(int c, double v0, double v1, double v2, const float *zj)
+{
+    using CH = Ch<O0, O1>;
+    if (c == CH::U) return (float)v0;
+    if (c == CH::X) return (float)(v1 * (double)zj[CH::X]);
+    if (c == CH::XX) return (float)(v2 * ((double)zj[CH::X] * (double)zj[CH::X]) + v1 * (double)zj[CH::XX]);
+    if (c == CH::Y) return (float)(v1 * (double)zj[CH::Y]);
+    return (float)(v2 * ((double)zj[CH::Y] * (double)zj[CH::Y]) + v1 * (double)zj[CH::YY]);
+}
+
+// Jets of a chunk's input il at point p: a hidden layer reads its saved
+// jets [C][win][n]; the first layer the coordinates x [n][2] (input il is
+// coordinate il, with unit first derivative along its own direction).
+template <int O0, int O1, bool FIRST>
+__device__ __forceinline__ float jet_in(const float *__restrict__ zin, int c, int i, int win, int64_t n, int64_t p)
+{
+    if constexpr (FIRST) {
+        using CH = Ch<O0, O1>;
+        if (c == CH::U) return zin[2 * p + i];
+        if (c == CH::X) return i == 0 ? 1.f : 0.f;
+        if (c == CH::Y) return i == 1 ? 1.f : 0.f;
+        return 0.f;
+    } else {
+        return zin[(int64_t)(c * win + i) * n + p];
+    }
+}
+
+// Build the K list of the tile's chunk of inputs [i0, i0 + TKJ): each lane
+// group g (16 lanes, one per point) takes inputs g, g + 4, g + 8, g + 12 and
+// reduces the window starts over the tile's live points; then every lane
+// reads the 16 row counts and writes its share of the entries.
+template <int KJ>
+__device__ __forceinline__ void build_klist(const float (*zv)[TPT], int lane, int64_t p0, int64_t n, float lo,
+                                            float inv_w, int nb, int *r0s, int *cnts, int nin = KJ)
+{
+    const int p = lane & 15, g = lane >> 4;
+    const bool pt_ok = p0 + p < n;
+#pragma unroll
+    for (int q = 0; q < KJ / 4; ++q) {
+        const int il = g + 4 * q;
+        const bool in_ok = il < nin;               // inputs nin.. of the capacity: no rows
+        const float zt = ((in_ok ? zv[il][p] : 0.f) - lo) * inv_w;
+        // live: inside the extended grid (-1.5, nb/2) in the scaled coordinate, or NaN
+        const bool live = in_ok && pt_ok && !(zt <= -1.5f) && !(zt >= 0.5f * (float)nb);
+        const int qa = (int)fminf(fmaxf(2.f * zt, 0.f), (float)(nb - 4));
+        int lo_q = live ? qa : 1 << 20, hi_q = live ? qa : -1;
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) {
+            lo_q = min(lo_q, __shfl_xor(lo_q, m, 16));
+            hi_q = max(hi_q, __shfl_xor(hi_q, m, 16));
+        }
+        if (p == 0) {
+            r0s[il] = hi_q < 0 ? 0 : lo_q;
+            cnts[il] = hi_q < 0 ? 0 : min(hi_q + 3, nb - 1) - lo_q + 1;
+        }
+    }
+}
+
+// The K list from the row counts: entries e = lane, lane + 64, .. get
+// (input << 8 | row); returns the number of entries.
+template <int KJ>
+__device__ __forceinline__ int write_entries(unsigned short *ent, int lane, const int *r0s, const int *cnts)
+{
+    int tot = 0;
+    int offs[KJ];
+#pragma unroll
+    for (int il = 0; il < KJ; ++il) {
+        offs[il] = tot;
+        tot += cnts[il];
+    }
+    for (int e = lane; e < tot; e += 64) {
+        int il = 0, base = 0;
+#pragma unroll
+        for (int q = 1; q < KJ; ++q)
+            if (e >= offs[q]) {
+                il = q;
+                base = offs[q];
+            }
+        ent[e] = (unsigned short)((il << 8) | (r0s[il] + e - base));
+    }
+    return tot;
+}
+
+// v', v'', v''' of bump b at FP32 input z, in FP64 (v[0] unused), for the
+// adjoint of the features; zero off the open support, a NaN input carried.
+__device__ __forceinline__ void bump_d123d(double2 kn, float z, double inv_w, double *v)
+{
+    const double zd = (double)z;
+    const double a = (zd - kn.x) * inv_w, be = (kn.y - zd) * inv_w;
+    const bool in = !(a <= 0.0) && !(be <= 0.0);
+    const double t = a * be, d = be - a, t2 = t * t;
+    const double w2 = inv_w * inv_w;
+    v[0] = 0.0;
+    v[1] = in ? (4.0 * inv_w) * (t2 * t) * d : 0.0;
+    v[2] = in ? (4.0 * w2) * t2 * (3.0 * d * d - 2.0 * t) : 0.0;
+    v[3] = in ? (24.0 * w2 * inv_w) * t * d * (d * d - 3.0 * t) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// forward: zout[c][j][p] = sum over the tile's K entries (i, b) of
+// A_c(p, i, b) W[i nb + b][j]. A wave takes a tile and all its outputs; each
+// lane owns output columns j = col * NT16 + ot (ot < NT16), so its B operands
+// of one K entry are NT16 consecutive floats of the weight row. The K steps
+// are software-pipelined: a step's MFMAs are issued before the next step's
+// A operands are computed, and the B operands are loaded a step ahead.
+// ---------------------------------------------------------------------------
+// waves per SIMD the forward and input-bar kernels are built for: a
+// 128-output layer keeps all its accumulators in one wave's registers
+template <int NT16> constexpr int tc_waves() { return NT16 > 4 ? 1 : 2; }
+
+template <int O0, int O1, bool FIRST, int NT16>
+__global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_fwd_tc(const float *__restrict__ zin, const float *__restrict__ W,
+                                                float *__restrict__ zout, int64_t n, int win, TcGrid gr)
+{
+    constexpr int C = 1 + O0 + O1;
+    constexpr int N = 16 * NT16;
+    constexpr int NTW = NT16;                       // 16-output tiles per wave
+    constexpr int WPT = NT16 / NTW;                 // waves per tile
+    constexpr int TPB = TW / WPT;                   // tiles per block round
+    __shared__ TcLds<O0, O1> lds[TW];
+    __shared__ double2 knots[MAXNB];
+    __shared__ int r0s_s[TW][TKJ], cnt_s[TW][TKJ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    TcLds<O0, O1> &L = lds[wv];
+    int *r0s = r0s_s[wv], *cnts = cnt_s[wv];
+    const int nb = gr.nb;
+    const float inv_w = gr.inv_w, lo = gr.lo;
+    const double inv_wd = gr.inv_w_d;
+    if (threadIdx.x < nb) knots[threadIdx.x] = make_double2(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    __syncthreads();
+    const int64_t ntiles = (n + TPT - 1) / TPT;
+    const int nchunk = FIRST ? 1 : win / TKJ;
+    const int nin = FIRST ? win : TKJ;
+
+    const int oh = wv % WPT;                        // this wave's output part
+    const int64_t tfirst = (int64_t)blockIdx.x * TPB + wv / WPT;
+    const int64_t tstride = (int64_t)gridDim.x * TPB;
+    // a chunk's jets: lane (r16 = point, g) holds inputs g, g + 4, .. in
+    // registers; the next chunk's are loaded while the current one computes
+    float pz[C][TKJ / 4];
+    auto load_chunk = [&](int64_t tl, int chn) {
+        const int64_t p = tl * TPT + r16;
+        const bool ok = tl < ntiles && p < n;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int q = 0; q < TKJ / 4; ++q) {
+                const int il = g + 4 * q;
+                pz[c][q] = (ok && il < nin) ? jet_in<O0, O1, FIRST>(zin, c, chn * TKJ + il, win, n, p) : 0.f;
+            }
+    };
+    load_chunk(tfirst, 0);
+
+    for (int64_t tile = tfirst; tile < ntiles; tile += tstride) {
+        const int64_t p0 = tile * TPT;
+        f4 acc[C][NTW];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int o = 0; o < NTW; ++o) acc[c][o] = (f4){0.f, 0.f, 0.f, 0.f};
+
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int i0 = ch * TKJ;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int q = 0; q < TKJ / 4; ++q) L.z[c][g + 4 * q][r16] = pz[c][q];
+            if (ch + 1 < nchunk)
+                load_chunk(tile, ch + 1);
+            else
+                load_chunk(tile + tstride, 0);
+            __builtin_amdgcn_wave_barrier();
+            build_klist<TKJ>(L.z[0], lane, p0, n, lo, inv_w, nb, r0s, cnts, nin);
+            __builtin_amdgcn_wave_barrier();
+            const int tot = write_entries<TKJ>(L.ent, lane, r0s, cnts);
+            __builtin_amdgcn_wave_barrier();
+            const int nsteps = (tot + 3) / 4;
+            // B operands of step s: this lane's NTW columns of row (i0 + il) nb + b
+            auto load_b = [&](int s, float *bw) {
+                const int e = 4 * s + g;
+                if (e < tot) {
+                    const int en = L.ent[e];
+                    const int row = (i0 + (en >> 8)) * nb + (en & 0xFF);
+                    const float *src = W + (int64_t)row * N + oh * 16 * NTW + r16 * NTW;
+                    if constexpr (NTW % 4 == 0) {
+#pragma unroll
+                        for (int o = 0; o < NTW; o += 4) {
+                            const f4 w4 = *reinterpret_cast<const f4 *>(src + o);
+                            bw[o] = w4[0];
+                            bw[o + 1] = w4[1];
+                            bw[o + 2] = w4[2];
+                            bw[o + 3] = w4[3];
+                        }
+                    } else {
+                        static_assert(NTW == 2, "32, 64 or 128 outputs");
+                        const float2 w2 = *reinterpret_cast<const float2 *>(src);
+                        bw[0] = w2.x;
+                        bw[1] = w2.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int o = 0; o < NTW; ++o) bw[o] = 0.f;
+                }
+            };
+            // A operands of step s: point r16, entry 4 s + g
+            auto comp_a = [&](int s, float *A) {
+                const int e = 4 * s + g;
+                if (e < tot) {
+                    const int en = L.ent[e];
+                    const int il = en >> 8, b = en & 0xFF;
+                    float zj[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) zj[c] = L.z[c][il][r16];
+                    double v0, v1, v2;
+                    bump3d(knots[b], zj[0], inv_wd, v0, v1, v2);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) A[c] = feature<O0, O1>(c, v0, v1, v2, zj);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) A[c] = 0.f;
+                }
+            };
+            float bcur[NTW], bnxt[NTW], acur[C], anxt[C];
+            if (nsteps > 0) {
+                load_b(0, bcur);
+                comp_a(0, acur);
+            }
+            for (int s = 0; s < nsteps; ++s) {
+                if (s + 1 < nsteps) load_b(s + 1, bnxt);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int o = 0; o < NTW; ++o)
+                        acc[c][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[c], bcur[o], acc[c][o], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);     // the next operands after this step's MFMAs
+                if (s + 1 < nsteps) comp_a(s + 1, anxt);
+#pragma unroll
+                for (int o = 0; o < NTW; ++o) bcur[o] = bnxt[o];
+#pragma unroll
+                for (int c = 0; c < C; ++c) acur[c] = anxt[c];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // D[4 g + r][r16] of tile o: point p0 + 4 g + r, output
+        // oh 16 NTW + r16 NTW + o; the lane's 4 values are consecutive points
+        // of one output row
+        const int64_t pg = p0 + 4 * g;
+        const bool vec = (n % 4 == 0) && pg + 3 < n;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int o = 0; o < NTW; ++o) {
+                const int j = oh * 16 * NTW + r16 * NTW + o;
+                float *dst = zout + (int64_t)(c * N + j) * n + pg;
+                if (vec) {
+                    *reinterpret_cast<f4 *>(dst) = acc[c][o];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (pg + r < n) dst[r] = acc[c][o][r];
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// input bars: Abar_c(p, i, b) = sum_j W[i nb + b][j] ybar[c][j][p] over the
+// tile's K entries (i, b), on the 16x16x4 FP32 MFMA with the entries as the
+// M axis (A = 16 weight rows), the points as the N axis (B = the output bars)
+// and the outputs as the reduction axis. Lane (g, r16) holds the B operands
+// ybar[c][16 s + 4 g + q][p0 + r16] of its pass's outputs in registers (at
+// most 64 outputs per pass, 32 for four or five channels of a 64-output
+// layer; every pass after the first adds to the result); the matching A
+// operand is the weight
+// W[row][16 s + 4 g + q], four consecutive floats of the row per s.
+// The adjoint of each feature through v', v'', v''' gives the entry's terms
+// of zbar[.][i][p]; they are staged per entry block and summed per input in
+// entry order, so every sum has one fixed order.
+// ---------------------------------------------------------------------------
+template <int O0, int O1>
+struct TcDxLds {
+    static constexpr int C = 1 + O0 + O1;
+    float z[C][TKJ][TPT];
+    float zb[C][TKJ][TPT];              // the chunk's input bars, summed over entries
+    float tm[16][C][TPT];               // the terms of one entry block
+    unsigned short ent[MAXK];
+};
+
+template <int O0, int O1, int NT16>
+__global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__restrict__ zin, const float *__restrict__ ybar,
+                                                  const float *__restrict__ W, float *__restrict__ zbar, int64_t n,
+                                                  int win, TcGrid gr)
+{
+    constexpr int C = 1 + O0 + O1;
+    constexpr int N = 16 * NT16;
+    // 16-output groups per pass (the registers of a pass's bars stay within
+    // two waves per SIMD) and passes over the outputs
+    constexpr int NS = NT16 > 4 ? 4 : (NT16 == 4 && C >= 4 ? 2 : NT16);
+    constexpr int NP = NT16 / NS;
+    __shared__ TcDxLds<O0, O1> lds[TW];
+    __shared__ double2 knots[MAXNB];
+    __shared__ int r0s_s[TW][TKJ], cnt_s[TW][TKJ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    TcDxLds<O0, O1> &L = lds[wv];
+    int *r0s = r0s_s[wv], *cnts = cnt_s[wv];
+    const int nb = gr.nb;
+    const float inv_w = gr.inv_w, lo = gr.lo;
+    const double inv_wd = gr.inv_w_d;
+    if (threadIdx.x < nb) knots[threadIdx.x] = make_double2(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    __syncthreads();
+    const int64_t ntiles = (n + TPT - 1) / TPT;
+    const int nchunk = win / TKJ;
+
+    const int64_t tstride = (int64_t)gridDim.x * TW;
+    // a chunk's jets in registers, the next chunk's loaded during the current one
+    float pz[C][TKJ / 4];
+    auto load_chunk = [&](int64_t tl, int chn) {
+        const int64_t p = tl * TPT + r16;
+        const bool ok = tl < ntiles && p < n;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int q = 0; q < TKJ / 4; ++q)
+                pz[c][q] = ok ? zin[(int64_t)(c * win + chn * TKJ + g + 4 * q) * n + p] : 0.f;
+    };
+    load_chunk((int64_t)blockIdx.x * TW + wv, 0);
+
+    for (int64_t tile = (int64_t)blockIdx.x * TW + wv; tile < ntiles; tile += tstride) {
+        const int64_t p0 = tile * TPT;
+        const int64_t pl = p0 + r16;
+        const bool pl_ok = pl < n;
+#pragma unroll 1
+        for (int pass = 0; pass < NP; ++pass) {
+            const int j0 = pass * 16 * NS;
+            float yb[C][NS][4];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int sg = 0; sg < NS; ++sg)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        yb[c][sg][q] = pl_ok ? ybar[(int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + pl] : 0.f;
+
+#pragma unroll 1
+            for (int chn = 0; chn < nchunk; ++chn) {
+                const int i0 = chn * TKJ;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int q = 0; q < TKJ / 4; ++q) {
+                        const int il = g + 4 * q;
+                        L.z[c][il][r16] = pz[c][q];
+                        L.zb[c][il][r16] = 0.f;
+                    }
+                if (chn + 1 < nchunk)
+                    load_chunk(tile, chn + 1);
+                else if (pass + 1 < NP)
+                    load_chunk(tile, 0);
+                else
+                    load_chunk(tile + tstride, 0);
+                __builtin_amdgcn_wave_barrier();
+                build_klist<TKJ>(L.z[0], lane, p0, n, lo, inv_w, nb, r0s, cnts);
+                __builtin_amdgcn_wave_barrier();
+                const int tot = write_entries<TKJ>(L.ent, lane, r0s, cnts);
+                __builtin_amdgcn_wave_barrier();
+                const int nblk = (tot + 15) / 16;
+#pragma unroll 1
+                for (int eb = 0; eb < nblk; ++eb) {
+                    // A operand rows: entry eb*16 + r16
+                    const int em = eb * 16 + r16;
+                    const bool em_ok = em < tot;
+                    int wrow = 0;
+                    if (em_ok) {
+                        const int en = L.ent[em];
+                        wrow = (i0 + (en >> 8)) * nb + (en & 0xFF);
+                    }
+                    const float *wsrc = W + (int64_t)wrow * N + j0 + 4 * g;
+                    f4 acc[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int sg = 0; sg < NS; ++sg) {
+                        const f4 w4 =
+                            em_ok ? *reinterpret_cast<const f4 *>(wsrc + 16 * sg) : (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+#pragma unroll
+                            for (int c = 0; c < C; ++c)
+                                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[q], yb[c][sg][q], acc[c], 0, 0, 0);
+                    }
+                    // acc[c][r] = Abar_c(point r16, entry eb*16 + 4 g + r):
+                    // the entry's terms of the input bars
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int e = eb * 16 + 4 * g + r;
+                        float zc[C];
+#pragma unroll
+                        for (int c = 0; c < C; ++c) zc[c] = 0.f;
+                        if (e < tot) {
+                            const int en = L.ent[e];
+                            const int il = en >> 8, b = en & 0xFF;
+                            double zj[C], Ab[C], v[4], zd[C];
+#pragma unroll
+                            for (int c = 0; c < C; ++c) {
+                                zj[c] = (double)L.z[c][il][r16];
+                                Ab[c] = (double)acc[c][r];
+                                zd[c] = 0.0;
+                            }
+                            bump_d123d(knots[b], L.z[0][il][r16], inv_wd, v);
+                            features_adjoint<double, O0, O1>(v, zj, Ab, zd);
+#pragma unroll
+                            for (int c = 0; c < C; ++c) zc[c] = (float)zd[c];
+                        }
+#pragma unroll
+                        for (int c = 0; c < C; ++c) L.tm[4 * g + r][c][r16] = zc[c];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    // per (channel, point): the block's entries in order, one
+                    // running sum per input
+                    const int ne = min(16, tot - eb * 16);
+                    for (int cp = lane; cp < C * TPT; cp += 64) {
+                        const int c = cp / TPT, p = cp % TPT;
+                        int cur = L.ent[eb * 16] >> 8;
+                        float run = 0.f;
+                        for (int e = 0; e < ne; ++e) {
+                            const int il = L.ent[eb * 16 + e] >> 8;
+                            if (il != cur) {
+                                L.zb[c][cur][p] += run;
+                                run = 0.f;
+                                cur = il;
+                            }
+                            run += L.tm[e][c][p];
+                        }
+                        L.zb[c][cur][p] += run;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+                // the chunk's input bars (the second pass adds to the first's)
+                if (pl_ok)
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+#pragma unroll
+                        for (int q = 0; q < TKJ / 4; ++q) {
+                            const int il = g + 4 * q;
+                            float *dst = zbar + (int64_t)(c * win + i0 + il) * n + pl;
+                            const float v = L.zb[c][il][r16];
+                            *dst = pass == 0 ? v : *dst + v;
+                        }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: gW[i nb + b][j] = sum_p sum_c A_c(p, i, b) ybar[c][j][p].
+// A block takes TDI inputs and one slice of the points; wave w takes the 32
+// outputs 32 (w % OG) .. + 31 (OG = N / 32 output groups) and every
+// (4 / OG)-th tile of the slice. For a tile, the entries of the block's
+// inputs (its K list) form the M axis in blocks of 16, the outputs the N
+// axis, and the 16 points the reduction axis in 4 steps of 4 (lane group g
+// takes point 4 g + s in step s), on the 16x16x4 FP32 MFMA; each entry
+// block's 16 x 32 result is added into the wave's LDS copy of the block's
+// gradient rows (every element by one lane, so in a fixed order). At the
+// end the copies of the waves that share outputs are summed in wave order
+// and written as the slice's partial rows (reduced over slices in FP64).
+// ---------------------------------------------------------------------------
+constexpr int TDI = 6;              // inputs per gradient block
+constexpr int TDJ = 8;              // lane-group capacity of the K list builder (>= TDI)
+
+template <int O0, int O1>
+struct TcDwLds {
+    static constexpr int C = 1 + O0 + O1;
+    float z[C][TDI][TPT];
+    unsigned short ent[TDI * MAXNB];
+};
+
+template <int O0, int O1, bool FIRST, int NT16>
+__global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin, const float *__restrict__ ybar,
+                                                  float *__restrict__ part, int64_t n, int win, int nsplit,
+                                                  int64_t slice_pts, TcGrid gr)
+{
+    constexpr int C = 1 + O0 + O1;
+    constexpr int N = 16 * NT16;
+    constexpr int OG = NT16 / 2;                // 32-output groups
+    constexpr int TPH = TW / OG;                // waves per output group (tile phases)
+    extern __shared__ __align__(16) float dsm[];
+    __shared__ TcDwLds<O0, O1> lds[TW];
+    __shared__ double2 knots[MAXNB];
+    __shared__ int r0s_s[TW][TDJ], cnt_s[TW][TDJ];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int og = wv % OG, ph = wv / OG;
+    TcDwLds<O0, O1> &L = lds[wv];
+    int *r0s = r0s_s[wv], *cnts = cnt_s[wv];
+    const int nb = gr.nb;
+    const float inv_w = gr.inv_w, lo = gr.lo;
+    const double inv_wd = gr.inv_w_d;
+    const int i0 = blockIdx.x * TDI;
+    const int nin = min(TDI, win - i0);
+    const int rows = nin * nb;
+    float *grad = dsm + (size_t)wv * TDI * nb * 32;        // [row][32]
+    if (threadIdx.x < nb) knots[threadIdx.x] = make_double2(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    for (int e = lane; e < TDI * nb * 32; e += 64) grad[e] = 0.f;
+    __syncthreads();
+    const int64_t ps = (int64_t)blockIdx.y * slice_pts;
+    const int64_t pe = min(n, ps + slice_pts);
+    const int64_t ntl = ps < pe ? (pe - ps + TPT - 1) / TPT : 0;
+    const bool vec = (n % 4) == 0;
+
+    // a tile's jets of the block's inputs and its B operands
+    // ybar[c][32 og + 16 ot + r16][p0 + 4 g + s] (s = 0..3), in registers;
+    // the next tile's are loaded while the current one computes (zero past
+    // the slice end)
+    constexpr int NQ = (TDI + 3) / 4;
+    float pz[C][NQ];
+    f4 py[C][2];
+    auto load_tile = [&](int64_t t_) {
+        const bool tok = t_ < ntl;
+        const int64_t p0_ = ps + t_ * TPT;
+        const int64_t p = p0_ + r16;
+        const bool ok = tok && p < pe;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int il = g + 4 * q;
+                pz[c][q] = (ok && il < nin) ? jet_in<O0, O1, FIRST>(zin, c, i0 + il, win, n, p) : 0.f;
+            }
+        const int64_t pg = p0_ + 4 * g;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot) {
+                const float *src = ybar + (int64_t)(c * N + 32 * og + 16 * ot + r16) * n + pg;
+                if (tok && vec && pg + 3 < pe) {
+                    py[c][ot] = *reinterpret_cast<const f4 *>(src);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) py[c][ot][s] = (tok && pg + s < pe) ? src[s] : 0.f;
+                }
+            }
+    };
+    load_tile(ph);
+
+#pragma unroll 1
+    for (int64_t t = ph; t < ntl; t += TPH) {
+        const int64_t p0 = ps + t * TPT;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (g + 4 * q < TDI) L.z[c][g + 4 * q][r16] = pz[c][q];
+        f4 yv[C][2];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            yv[c][0] = py[c][0];
+            yv[c][1] = py[c][1];
+        }
+        load_tile(t + TPH);
+        __builtin_amdgcn_wave_barrier();
+        build_klist<TDJ>(L.z[0], lane, p0, pe, lo, inv_w, nb, r0s, cnts, nin);
+        __builtin_amdgcn_wave_barrier();
+        const int tot = write_entries<TDJ>(L.ent, lane, r0s, cnts);
+        __builtin_amdgcn_wave_barrier();
+        const int nblk = (tot + 15) / 16;
+#pragma unroll 1
+        for (int eb = 0; eb < nblk; ++eb) {
+            const int em = eb * 16 + r16;              // this lane's A row (entry)
+            const bool em_ok = em < tot;
+            int il = 0, b = 0;
+            if (em_ok) {
+                const int en = L.ent[em];
+                il = en >> 8;
+                b = en & 0xFF;
+            }
+            const double2 kn = knots[b];
+            f4 acc[2] = {(f4){0.f, 0.f, 0.f, 0.f}, (f4){0.f, 0.f, 0.f, 0.f}};
+            // features of step s (point 4 g + s); the next step's are computed
+            // after this step's MFMAs are issued
+            auto comp_a = [&](int s, float *A) {
+                const int pt = 4 * g + s;
+                float zj[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) zj[c] = L.z[c][il][pt];
+                double v0, v1, v2;
+                bump3d(kn, zj[0], inv_wd, v0, v1, v2);
+#pragma unroll
+                for (int c = 0; c < C; ++c) A[c] = em_ok ? feature<O0, O1>(c, v0, v1, v2, zj) : 0.f;
+            };
+            float A0[C], A1[C];
+            comp_a(0, A0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                float *Ac = (s & 1) ? A1 : A0;
+                float *An = (s & 1) ? A0 : A1;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int ot = 0; ot < 2; ++ot)
+                        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[c], yv[c][ot][s], acc[ot], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (s < 3) comp_a(s + 1, An);
+            }
+            // acc[ot][r] = D[entry eb*16 + 4 g + r][output 16 ot + r16]
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = eb * 16 + 4 * g + r;
+                if (e < tot) {
+                    const int en = L.ent[e];
+                    const int row = (en >> 8) * nb + (en & 0xFF);
+#pragma unroll
+                    for (int ot = 0; ot < 2; ++ot) grad[row * 32 + 16 * ot + r16] += acc[ot][r];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // the slice's partial rows: the tile phases of each output group summed
+    // in wave order
+    float *dst = part + (int64_t)blockIdx.y * ((int64_t)win * nb * N) + (int64_t)i0 * nb * N;
+    for (int e = threadIdx.x; e < rows * N; e += TNT) {
+        const int row = e / N, j = e % N;
+        const int o = j / 32, jj = j % 32;
+        float v = 0.f;
+#pragma unroll
+        for (int q = 0; q < TPH; ++q) v += dsm[(size_t)(q * OG + o) * TDI * nb * 32 + row * 32 + jj];
+        dst[(int64_t)row * N + j] = v;
+    }
+}
+
+#define HRK_TC_CH_SWITCH(ch, ...)                                  \
+    switch ((ch).o0 * 3 + (ch).o1) {                               \
+    case 0: { constexpr int O0 = 0, O1 = 0; __VA_ARGS__; } break;  \
+    case 4: { constexpr int O0 = 1, O1 = 1; __VA_ARGS__; } break;  \
+    case 6: { constexpr int O0 = 2, O1 = 0; __VA_ARGS__; } break;  \
+    case 7: { constexpr int O0 = 2, O1 = 1; __VA_ARGS__; } break;  \
+    case 8: { constexpr int O0 = 2, O1 = 2; __VA_ARGS__; } break;  \
+    default: return hipErrorInvalidValue;                          \
+    }
+
+#define HRK_TC_N_SWITCH(N, ...)                                    \
+    switch (N) {                                                   \
+    case 32: { constexpr int NT16 = 2; __VA_ARGS__; } break;       \
+    case 64: { constexpr int NT16 = 4; __VA_ARGS__; } break;       \
+    case 128: { constexpr int NT16 = 8; __VA_ARGS__; } break;      \
+    default: return hipErrorInvalidValue;                          \
+    }
+
+int grid_of(int64_t n, int cu_blocks, int tiles_per_block = TW)
+{
+    const int64_t tiles = (n + TPT - 1) / TPT;
+    const int64_t blocks = (tiles + tiles_per_block - 1) / tiles_per_block;
+    const int64_t cap = (int64_t)cu_blocks * 4;
+    return (int)std::max<int64_t>(1, std::min(blocks, cap));
+}
+
+}  // namespace
+
+bool tc_supported(ChanCfg ch, LayerShape ls, int k, int m, bool first)
+{
+    const int cs = ch.o0 * 3 + ch.o1;
+    const bool chan_ok = cs == 0 || cs == 4 || cs == 6 || cs == 7 || cs == 8;
+    const bool in_ok = first ? ls.win == 2 : ls.win % TKJ == 0;
+    return chan_ok && in_ok && k == 3 && m == 4 && ls.nb >= 4 && ls.nb <= MAXNB &&
+           (ls.wout == 32 || ls.wout == 64 || ls.wout == 128);
+}
+
+TcGrid make_tc_grid(double lo, double hi, int G, int k)
+{
+    TcGrid t{};
+    const int nb = G + k;
+    const double h = (hi - lo) / G;
+    t.nb = nb;
+    t.lo = (float)lo;
+    t.inv_w = (float)(2.0 / ((k + 1) * h));
+    t.inv_w_d = 2.0 / ((k + 1) * h);
+    for (int b = 0; b < nb && b < MAXNB; ++b) {
+        t.s[b] = lo + (b - k) * h;
+        t.e[b] = lo + (b + 1) * h;
+    }
+    return t;
+}
+
+hipError_t launch_fwd_tc(ChanCfg ch, bool first, const float *zin, const float *W, float *zout, int64_t n,
+                         LayerShape ls, const TcGrid &gr, int cu_blocks, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (!tc_supported(ch, ls, 3, 4, first)) return hipErrorInvalidValue;
+    const int grid = grid_of(n, cu_blocks);
+    HRK_TC_CH_SWITCH(ch, {
+        HRK_TC_N_SWITCH(ls.wout, {
+            if (first)
+                hipLaunchKernelGGL((k_fwd_tc<O0, O1, true, NT16>), dim3(grid), dim3(TNT), 0, st, zin, W, zout, n,
+                                   ls.win, gr);
+            else
+                hipLaunchKernelGGL((k_fwd_tc<O0, O1, false, NT16>), dim3(grid), dim3(TNT), 0, st, zin, W, zout, n,
+                                   ls.win, gr);
+        });
+    });
+    return hipGetLastError();
+}
+
+
+
+hipError_t launch_dx_tc(ChanCfg ch, const float *zin, const float *ybar, const float *W, float *zbar, int64_t n,
+                        LayerShape ls, const TcGrid &gr, int cu_blocks, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (!tc_supported(ch, ls, 3, 4, false)) return hipErrorInvalidValue;
+    const int grid = grid_of(n, cu_blocks);
+    HRK_TC_CH_SWITCH(ch, {
+        HRK_TC_N_SWITCH(ls.wout, {
+            hipLaunchKernelGGL((k_dx_tc<O0, O1, NT16>), dim3(grid), dim3(TNT), 0, st, zin, ybar, W, zbar, n,
+                               ls.win, gr);
+        });
+    });
+    return hipGetLastError();
+}
+
+size_t dw_tc_lds_bytes(int nb) { return sizeof(float) * (size_t)TW * TDI * nb * 32; }
+
+// Raise a kernel's dynamic-LDS limit to `bytes` when its last setting is
+// lower (the first launch of each kernel and size happens eagerly, outside
+// any graph capture). Kernels are told apart by their address.
+hipError_t raise_lds(int, const void *kf, size_t bytes)
+{
+    static const void *fn[64];
+    static size_t lim[64];
+    static int nfn = 0;
+    int k = 0;
+    while (k < nfn && fn[k] != kf) ++k;
+    if (k < nfn && lim[k] >= bytes) return hipSuccess;
+    if (bytes <= 64 * 1024) return hipSuccess;         // the default limit
+    const hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    if (k == nfn && nfn < 64) fn[nfn++] = kf;
+    if (k < 64) lim[k] = bytes;
+    return hipSuccess;
+}
+
+int dw_tc_splits(int64_t n, LayerShape ls)
+{
+    if (n <= 0) return 0;
+    // two rounds of two blocks per CU over the input groups and point
+    // slices (rounded down, so the last round is not a sliver), with at
+    // least 256 points per slice
+    const int64_t groups = (ls.win + TDI - 1) / TDI;
+    const int64_t s = std::max<int64_t>(1, 1024 / groups);
+    const int64_t maxs = std::max<int64_t>(1, n / 256);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(s, maxs), 4096));
+}
+
+hipError_t launch_dw_tc(ChanCfg ch, bool first, const float *zin, const float *ybar, float *part, int nsplit,
+                        int64_t n, LayerShape ls, const TcGrid &gr, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (!tc_supported(ch, ls, 3, 4, first) || nsplit < 1) return hipErrorInvalidValue;
+    int64_t slice = (n + nsplit - 1) / nsplit;
+    slice = (slice + TPT - 1) / TPT * TPT;
+    const dim3 grid((unsigned)((ls.win + TDI - 1) / TDI), (unsigned)nsplit);
+    const size_t sh = dw_tc_lds_bytes(ls.nb);
+    HRK_TC_CH_SWITCH(ch, {
+        HRK_TC_N_SWITCH(ls.wout, {
+            auto kf = first ? k_dw_tc<O0, O1, true, NT16> : k_dw_tc<O0, O1, false, NT16>;
+            const hipError_t e = raise_lds(first ? 1 : 0, (const void *)kf, sh);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kf, grid, dim3(TNT), sh, st, zin, ybar, part, n, ls.win, nsplit, slice, gr);
+        });
+    });
+    return hipGetLastError();
+}
+
+}  // namespace hrk

@@ -15,6 +15,8 @@
 #include "hrkan.h"
 #include "internal.h"
 #include "kernels_bs.h"
+#include "kernels_tc.h"
+#include "sort.h"
 #include "kernels_dn.h"
 #include "runtime_internal.h"
 
@@ -155,6 +157,34 @@ bool use_dn(const NetInfo &ni, int l)
 }
 
 
+// FP32 layers with 32, 64 or 128 outputs run on the tile-coherent kernels
+// (HRKAN_TC=0 in the environment keeps them on the block-sparse ones).
+bool tc_enabled()
+{
+    static const bool enabled = [] {
+        const char *e = getenv("HRKAN_TC");
+        return !(e && e[0] == '0');
+    }();
+    return enabled;
+}
+
+bool use_tc(const NetInfo &ni, int l)
+{
+    return tc_enabled() && ni.dtype == HRKAN_F32 &&
+           tc_supported(ChanCfg{2, 2}, LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, ni.k, ni.m, l == 0);
+}
+
+// A training step orders each point set along a Z-order curve first (in the
+// workspace) when its hidden layers run on the tile-coherent kernels and the
+// sets run separately (not merged).
+bool sorted_sets(const NetInfo &ni, int64_t n_int, int64_t n_bc)
+{
+    if (merged_sets(ni, n_int, n_bc) || n_int > ((int64_t)1 << 24) || n_bc > ((int64_t)1 << 24)) return false;
+    for (int l = 0; l < ni.L; ++l)
+        if (use_tc(ni, l)) return true;
+    return false;
+}
+
 size_t wdn_offset(const NetInfo &ni, int l)
 {
     size_t o = 0;
@@ -184,6 +214,7 @@ int dw_splits(const NetInfo &ni, int l, int64_t n)
     if (n <= 0) return 0;
     const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
     if (use_dn(ni, l)) return dw_dn_splits(n, ls);
+    if (use_tc(ni, l)) return dw_tc_splits(n, ls);
     return use_bs32(ni, l) ? dw_bs32_splits(n, ls) : dw_generic_splits(n, ls);
 }
 
@@ -330,6 +361,11 @@ WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
     L.part_elems = part_elems_total(ni, na, nbs);
     L.part = take(E * (size_t)L.part_elems);
     L.wdn = take(wdn_offset(ni, ni.L));
+    L.sorted = sorted_sets(ni, n_int, n_bc);
+    L.xs_int = take(L.sorted ? sizeof(float) * 2 * (size_t)n_int : 0);
+    L.xs_bc = take(L.sorted ? sizeof(float) * 2 * (size_t)n_bc : 0);
+    L.gs_bc = take(L.sorted ? sizeof(float) * (size_t)n_bc : 0);
+    L.sort_ws = take(L.sorted ? sort_ws_bytes(std::max(n_int, n_bc)) : 0);
     L.total = o;
     return L;
 }
@@ -380,6 +416,9 @@ int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, i
             if constexpr (std::is_same<T, float>::value) {
                 if (use_dn(ni, l))
                     e = launch_fwd_dn(ch, zin, wdn + wdn_offset(ni, l), zout, n, ls, g, ni.S, st);
+                else if (use_tc(ni, l))
+                    e = launch_fwd_tc(ch, l == 0, zin, W[l], zout, n, ls, make_tc_grid(ni.lo, ni.hi, ni.G, ni.k),
+                                      cu_blocks(), st);
                 else if (use_bs32(ni, l))
                     e = launch_fwd_bs32(ch, l == 0, zin, W[l], zout, n, ls, g, cu_blocks(), bf16_terms(ni), st);
                 else
@@ -444,6 +483,9 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             if constexpr (std::is_same<T, float>::value) {
                 if (use_dn(ni, l))
                     e = launch_dw_dn(S.ch, zin, ybar, dst, ns, S.n, ls, g, ni.S, st);
+                else if (use_tc(ni, l))
+                    e = launch_dw_tc(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, make_tc_grid(ni.lo, ni.hi, ni.G, ni.k),
+                                     st);
                 else if (use_bs32(ni, l))
                     e = launch_dw_bs32(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, g, bf16_terms(ni), st);
                 else
@@ -460,6 +502,9 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             if constexpr (std::is_same<T, float>::value) {
                 if (use_dn(ni, l))
                     e = launch_dx_dn(S.ch, zin, ybar, wdn + wdn_offset(ni, l), zbar, S.n, ls, g, ni.S, st);
+                else if (use_tc(ni, l))
+                    e = launch_dx_tc(S.ch, zin, ybar, W[l], zbar, S.n, ls, make_tc_grid(ni.lo, ni.hi, ni.G, ni.k),
+                                     cu_blocks(), st);
                 else if (use_bs32(ni, l))
                     e = launch_dx_bs32(S.ch, zin, ybar, W[l], zbar, S.n, ls, g, cu_blocks(), bf16_terms(ni), st);
                 else
@@ -812,6 +857,21 @@ int step_impl(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *
         // alone), forked before the forward pass and again after the
         // residual, joined after each pass. The interior set's launches are
         // enqueued first: it is the longer chain.
+        const T *x_int = (const T *)pts->x_int, *x_bc = (const T *)pts->x_bc, *g_bc = (const T *)pts->g_bc;
+        if constexpr (std::is_same<T, float>::value) {
+            if (L.sorted) {
+                float *xs = (float *)(w + L.xs_int), *xb = (float *)(w + L.xs_bc), *gb = (float *)(w + L.gs_bc);
+                {
+                    ProfScope ps("sort", -1, stream);
+                    e = launch_sort_points(x_int, nullptr, ni_, w + L.sort_ws, xs, nullptr, stream);
+                    if (e == hipSuccess) e = launch_sort_points(x_bc, g_bc, nb_, w + L.sort_ws, xb, gb, stream);
+                }
+                if (e != hipSuccess) return hip_fail(e, "point ordering launch");
+                x_int = xs;
+                x_bc = xb;
+                g_bc = gb;
+            }
+        }
         Fork *fk = nullptr;
         if (allow_fork && overlap_sets(ni, ni_, nb_) && !prof_on()) TRY(get_fork(stream, &fk));
         hipStream_t sb = fk ? fk->side : stream;
@@ -825,22 +885,21 @@ int step_impl(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *
                           loss_out,
                           (uint32_t *)w};
         RevSet<T> sets[2] = {
-            {chi, (const T *)pts->x_int, ni_, seed_int, sv_int, (T *)(w + L.bars0), (T *)(w + L.bars1)},
-            {chb, (const T *)pts->x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
+            {chi, x_int, ni_, seed_int, sv_int, (T *)(w + L.bars0), (T *)(w + L.bars1)},
+            {chb, x_bc, nb_, seed_bc, sv_bc, (T *)(w + L.bbars0), (T *)(w + L.bbars1)},
         };
         if (fk) TRY(fork_to(fk, stream));
         if (ni_ > 0)
-            TRY(forward_impl<T>(ni, chi, (const T *const *)W, (const T *)pts->x_int, ni_, jets, sv_int,
-                                nullptr, nullptr, stream, false, wdn));
+            TRY(forward_impl<T>(ni, chi, (const T *const *)W, x_int, ni_, jets, sv_int, nullptr, nullptr, stream,
+                                false, wdn));
         if (nb_ > 0)
-            TRY(forward_impl<T>(ni, chb, (const T *const *)W, (const T *)pts->x_bc, nb_, ubc, sv_bc,
-                                nullptr, nullptr, sb, true, wdn));
+            TRY(forward_impl<T>(ni, chb, (const T *const *)W, x_bc, nb_, ubc, sv_bc, nullptr, nullptr, sb, true,
+                                wdn));
         if (fk) TRY(join_from(fk, stream));
         {
             ProfScope ps("residual", -1, stream);
-            e = launch_residual<T>(pp, chi.C(), jets, (const T *)pts->x_int, ni_, ubc,
-                                   (const T *)pts->g_bc, nb_, nullptr, seed_int, seed_bc, partials,
-                                   L.nres, stream);
+            e = launch_residual<T>(pp, chi.C(), jets, x_int, ni_, ubc, g_bc, nb_, nullptr, seed_int, seed_bc,
+                                   partials, L.nres, stream);
         }
         if (e != hipSuccess) return hip_fail(e, "residual launch");
         if (fk) {

@@ -29,6 +29,8 @@ struct WsLayout {
     size_t status, loss_part, sv_int, jets_int, sv_bc, ubc, seed_int, seed_bc;
     size_t bars0, bars1, bbars0, bbars1, part;
     size_t wdn;                 // BF16 weight copies of the dense-kernel layers
+    bool sorted;                // the sets are reordered along a Z-order curve (sorted_sets)
+    size_t xs_int, xs_bc, gs_bc, sort_ws;
     int64_t part_elems;
     int nres;
     size_t total;
