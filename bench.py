@@ -37,7 +37,7 @@ METRIC = "PINN train-step collocation points/s (fwd jets+residual+bwd), bf16 vs 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}
 
 # the kernels and the launch sequence the counter summary was taken on
-KERNEL_SRC = [os.path.join(ROOT, "paper_2409_14248_amd", "csrc", f) for f in ("kernels_bs32.hip", "runtime.cpp")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_2409_14248_amd", "csrc", f) for f in ("kernels_tc.hip", "runtime.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_burgers_c4_f32.md")
 TRAFFIC_RUN = ("burgers_c4", "f32")     # the workload and dtype those counters were taken on
 

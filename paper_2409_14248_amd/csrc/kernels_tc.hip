@@ -95,6 +95,17 @@ __device__ __forceinline__ float jet_in(const float *__restrict__ zin, int c, in
     }
 }
 
+// jet_in at point p of input i when ok, else zero; the load is always issued
+// (at a valid point and input), so no load sits in a divergent branch, whose
+// join would make the compiler wait for every load in flight.
+template <int O0, int O1, bool FIRST>
+__device__ __forceinline__ float jet_sel(const float *__restrict__ zin, int c, int i, int win, int64_t n, int64_t p,
+                                         bool ok)
+{
+    const float v = jet_in<O0, O1, FIRST>(zin, c, ok ? i : 0, win, n, ok ? p : 0);
+    return ok ? v : 0.f;
+}
+
 // Build the K list of the tile's chunk of inputs [i0, i0 + TKJ): each lane
 // group g (16 lanes, one per point) takes inputs g, g + 4, g + 8, g + 12 and
 // reduces the window starts over the tile's live points; then every lane
@@ -170,13 +181,12 @@ __device__ __forceinline__ void bump_d123d(double2 kn, float z, double inv_w, do
 // forward: zout[c][j][p] = sum over the tile's K entries (i, b) of
 // A_c(p, i, b) W[i nb + b][j]. A wave takes a tile and all its outputs; each
 // lane owns output columns j = col * NT16 + ot (ot < NT16), so its B operands
-// of one K entry are NT16 consecutive floats of the weight row. The K steps
-// are software-pipelined: a step's MFMAs are issued before the next step's
-// A operands are computed, and the B operands are loaded a step ahead.
+// of one K entry are NT16 consecutive floats of the weight row, loaded a step
+// ahead.
 // ---------------------------------------------------------------------------
 // waves per SIMD the forward and input-bar kernels are built for: a
 // 128-output layer keeps all its accumulators in one wave's registers
-template <int NT16> constexpr int tc_waves() { return NT16 > 4 ? 1 : 2; }
+template <int NT16> constexpr int tc_waves() { return 2; }
 
 template <int O0, int O1, bool FIRST, int NT16>
 __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_fwd_tc(const float *__restrict__ zin, const float *__restrict__ W,
@@ -206,21 +216,6 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_fwd_tc(const float *_
     const int oh = wv % WPT;                        // this wave's output part
     const int64_t tfirst = (int64_t)blockIdx.x * TPB + wv / WPT;
     const int64_t tstride = (int64_t)gridDim.x * TPB;
-    // a chunk's jets: lane (r16 = point, g) holds inputs g, g + 4, .. in
-    // registers; the next chunk's are loaded while the current one computes
-    float pz[C][TKJ / 4];
-    auto load_chunk = [&](int64_t tl, int chn) {
-        const int64_t p = tl * TPT + r16;
-        const bool ok = tl < ntiles && p < n;
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int q = 0; q < TKJ / 4; ++q) {
-                const int il = g + 4 * q;
-                pz[c][q] = (ok && il < nin) ? jet_in<O0, O1, FIRST>(zin, c, chn * TKJ + il, win, n, p) : 0.f;
-            }
-    };
-    load_chunk(tfirst, 0);
 
     for (int64_t tile = tfirst; tile < ntiles; tile += tstride) {
         const int64_t p0 = tile * TPT;
@@ -232,83 +227,88 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_fwd_tc(const float *_
 
         for (int ch = 0; ch < nchunk; ++ch) {
             const int i0 = ch * TKJ;
+            // the chunk's jets: lane (r16 = point, g) loads inputs g, g + 4, ..
+            {
+                const int64_t p = p0 + r16;
+                const bool ok = p < n;
 #pragma unroll
-            for (int c = 0; c < C; ++c)
+                for (int c = 0; c < C; ++c)
 #pragma unroll
-                for (int q = 0; q < TKJ / 4; ++q) L.z[c][g + 4 * q][r16] = pz[c][q];
-            if (ch + 1 < nchunk)
-                load_chunk(tile, ch + 1);
-            else
-                load_chunk(tile + tstride, 0);
+                    for (int q = 0; q < TKJ / 4; ++q) {
+                        const int il = g + 4 * q;
+                        L.z[c][il][r16] = jet_sel<O0, O1, FIRST>(zin, c, i0 + il, win, n, p, ok && il < nin);
+                    }
+            }
             __builtin_amdgcn_wave_barrier();
             build_klist<TKJ>(L.z[0], lane, p0, n, lo, inv_w, nb, r0s, cnts, nin);
             __builtin_amdgcn_wave_barrier();
-            const int tot = write_entries<TKJ>(L.ent, lane, r0s, cnts);
+            // the same count in every lane: taken as a scalar, so the loop
+            // branches are uniform and no load waits at a divergent join
+            const int tot = __builtin_amdgcn_readfirstlane(write_entries<TKJ>(L.ent, lane, r0s, cnts));
             __builtin_amdgcn_wave_barrier();
             const int nsteps = (tot + 3) / 4;
-            // B operands of step s: this lane's NTW columns of row (i0 + il) nb + b
+            // B operands of step s: this lane's NTW columns of the row of
+            // entry 4 s + g (padding entries past tot read the last entry's
+            // row, their A operand is zero); no divergent branch, so the
+            // loads stay in flight across the MFMAs
             auto load_b = [&](int s, float *bw) {
-                const int e = 4 * s + g;
-                if (e < tot) {
-                    const int en = L.ent[e];
-                    const int row = (i0 + (en >> 8)) * nb + (en & 0xFF);
-                    const float *src = W + (int64_t)row * N + oh * 16 * NTW + r16 * NTW;
-                    if constexpr (NTW % 4 == 0) {
+                const int e = min(4 * s + g, tot - 1);
+                const int en = L.ent[e];
+                const int row = (i0 + (en >> 8)) * nb + (en & 0xFF);
+                const float *src = W + (int64_t)row * N + oh * 16 * NTW + r16 * NTW;
+                if constexpr (NTW % 4 == 0) {
 #pragma unroll
-                        for (int o = 0; o < NTW; o += 4) {
-                            const f4 w4 = *reinterpret_cast<const f4 *>(src + o);
-                            bw[o] = w4[0];
-                            bw[o + 1] = w4[1];
-                            bw[o + 2] = w4[2];
-                            bw[o + 3] = w4[3];
-                        }
-                    } else {
-                        static_assert(NTW == 2, "32, 64 or 128 outputs");
-                        const float2 w2 = *reinterpret_cast<const float2 *>(src);
-                        bw[0] = w2.x;
-                        bw[1] = w2.y;
+                    for (int o = 0; o < NTW; o += 4) {
+                        const f4 w4 = *reinterpret_cast<const f4 *>(src + o);
+                        bw[o] = w4[0];
+                        bw[o + 1] = w4[1];
+                        bw[o + 2] = w4[2];
+                        bw[o + 3] = w4[3];
                     }
                 } else {
-#pragma unroll
-                    for (int o = 0; o < NTW; ++o) bw[o] = 0.f;
+                    static_assert(NTW == 2, "32, 64 or 128 outputs");
+                    const float2 w2 = *reinterpret_cast<const float2 *>(src);
+                    bw[0] = w2.x;
+                    bw[1] = w2.y;
                 }
             };
-            // A operands of step s: point r16, entry 4 s + g
+            // A operands of step s: point r16, entry 4 s + g (zero past tot)
             auto comp_a = [&](int s, float *A) {
                 const int e = 4 * s + g;
-                if (e < tot) {
-                    const int en = L.ent[e];
-                    const int il = en >> 8, b = en & 0xFF;
-                    float zj[C];
+                const int en = L.ent[min(e, tot - 1)];
+                const int il = en >> 8, b = en & 0xFF;
+                float zj[C];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) zj[c] = L.z[c][il][r16];
-                    double v0, v1, v2;
-                    bump3d(knots[b], zj[0], inv_wd, v0, v1, v2);
+                for (int c = 0; c < C; ++c) zj[c] = L.z[c][il][r16];
+                double v0, v1, v2;
+                bump3d(knots[b], zj[0], inv_wd, v0, v1, v2);
 #pragma unroll
-                    for (int c = 0; c < C; ++c) A[c] = feature<O0, O1>(c, v0, v1, v2, zj);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) A[c] = 0.f;
+                for (int c = 0; c < C; ++c) {
+                    const float f = feature<O0, O1>(c, v0, v1, v2, zj);
+                    A[c] = e < tot ? f : 0.f;
                 }
             };
-            float bcur[NTW], bnxt[NTW], acur[C], anxt[C];
-            if (nsteps > 0) {
-                load_b(0, bcur);
-                comp_a(0, acur);
-            }
-            for (int s = 0; s < nsteps; ++s) {
-                if (s + 1 < nsteps) load_b(s + 1, bnxt);
+            // two B buffers used in turn: the loads of a step stay in flight
+            // while the previous step computes (no copies between them)
+            float b0[NTW], b1[NTW], a[C];
+            auto mma = [&](const float *bw) {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
 #pragma unroll
                     for (int o = 0; o < NTW; ++o)
-                        acc[c][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(acur[c], bcur[o], acc[c][o], 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);     // the next operands after this step's MFMAs
-                if (s + 1 < nsteps) comp_a(s + 1, anxt);
-#pragma unroll
-                for (int o = 0; o < NTW; ++o) bcur[o] = bnxt[o];
-#pragma unroll
-                for (int c = 0; c < C; ++c) acur[c] = anxt[c];
+                        acc[c][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], bw[o], acc[c][o], 0, 0, 0);
+            };
+            // steps in pairs; the prefetches past the last step read the last
+            // entry's row again and a step past it multiplies zeros, so every
+            // load is unconditional and the waits count loads exactly
+            if (nsteps > 0) load_b(0, b0);
+            for (int s = 0; s < nsteps; s += 2) {
+                load_b(s + 1, b1);
+                comp_a(s, a);
+                mma(b0);
+                load_b(s + 2, b0);
+                comp_a(s + 1, a);
+                mma(b1);
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int q = 0; q < TKJ / 4; ++q)
-                pz[c][q] = ok ? zin[(int64_t)(c * win + chn * TKJ + g + 4 * q) * n + p] : 0.f;
+                pz[c][q] = jet_sel<O0, O1, false>(zin, c, chn * TKJ + g + 4 * q, win, n, p, ok);
     };
     load_chunk((int64_t)blockIdx.x * TW + wv, 0);
 
@@ -411,7 +411,10 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
                 for (int sg = 0; sg < NS; ++sg)
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        yb[c][sg][q] = pl_ok ? ybar[(int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + pl] : 0.f;
+                    {
+                        const float v = ybar[(int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + (pl_ok ? pl : 0)];
+                        yb[c][sg][q] = pl_ok ? v : 0.f;
+                    }
 
 #pragma unroll 1
             for (int chn = 0; chn < nchunk; ++chn) {
@@ -433,58 +436,57 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
                 __builtin_amdgcn_wave_barrier();
                 build_klist<TKJ>(L.z[0], lane, p0, n, lo, inv_w, nb, r0s, cnts);
                 __builtin_amdgcn_wave_barrier();
-                const int tot = write_entries<TKJ>(L.ent, lane, r0s, cnts);
+                const int tot = __builtin_amdgcn_readfirstlane(write_entries<TKJ>(L.ent, lane, r0s, cnts));
                 __builtin_amdgcn_wave_barrier();
                 const int nblk = (tot + 15) / 16;
+                // A operands (weight rows) of entry block eb: entry eb*16 + r16,
+                // past tot the last entry's row (multiplied as zero); the next
+                // block's are loaded during the current block's work
+                auto load_w = [&](int eb_, f4 *w) {
+                    const int en = L.ent[min(eb_ * 16 + r16, tot - 1)];
+                    const int wrow = (i0 + (en >> 8)) * nb + (en & 0xFF);
+                    const float *wsrc = W + (int64_t)wrow * N + j0 + 4 * g;
+#pragma unroll
+                    for (int sg = 0; sg < NS; ++sg) w[sg] = *reinterpret_cast<const f4 *>(wsrc + 16 * sg);
+                };
+                f4 wcur[NS], wnxt[NS];
+                if (nblk > 0) load_w(0, wcur);
 #pragma unroll 1
                 for (int eb = 0; eb < nblk; ++eb) {
-                    // A operand rows: entry eb*16 + r16
-                    const int em = eb * 16 + r16;
-                    const bool em_ok = em < tot;
-                    int wrow = 0;
-                    if (em_ok) {
-                        const int en = L.ent[em];
-                        wrow = (i0 + (en >> 8)) * nb + (en & 0xFF);
-                    }
-                    const float *wsrc = W + (int64_t)wrow * N + j0 + 4 * g;
+                    load_w(eb + 1, wnxt);            // past the last block: the last entry's row again
+                    const bool em_ok = eb * 16 + r16 < tot;
                     f4 acc[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) acc[c] = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int sg = 0; sg < NS; ++sg) {
-                        const f4 w4 =
-                            em_ok ? *reinterpret_cast<const f4 *>(wsrc + 16 * sg) : (f4){0.f, 0.f, 0.f, 0.f};
+                        const f4 w4 = em_ok ? wcur[sg] : (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
 #pragma unroll
                             for (int c = 0; c < C; ++c)
                                 acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[q], yb[c][sg][q], acc[c], 0, 0, 0);
                     }
+#pragma unroll
+                    for (int sg = 0; sg < NS; ++sg) wcur[sg] = wnxt[sg];
                     // acc[c][r] = Abar_c(point r16, entry eb*16 + 4 g + r):
                     // the entry's terms of the input bars
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int e = eb * 16 + 4 * g + r;
-                        float zc[C];
+                        const int en = L.ent[min(e, tot - 1)];
+                        const int il = en >> 8, b = en & 0xFF;
+                        double zj[C], Ab[C], v[4], zd[C];
 #pragma unroll
-                        for (int c = 0; c < C; ++c) zc[c] = 0.f;
-                        if (e < tot) {
-                            const int en = L.ent[e];
-                            const int il = en >> 8, b = en & 0xFF;
-                            double zj[C], Ab[C], v[4], zd[C];
-#pragma unroll
-                            for (int c = 0; c < C; ++c) {
-                                zj[c] = (double)L.z[c][il][r16];
-                                Ab[c] = (double)acc[c][r];
-                                zd[c] = 0.0;
-                            }
-                            bump_d123d(knots[b], L.z[0][il][r16], inv_wd, v);
-                            features_adjoint<double, O0, O1>(v, zj, Ab, zd);
-#pragma unroll
-                            for (int c = 0; c < C; ++c) zc[c] = (float)zd[c];
+                        for (int c = 0; c < C; ++c) {
+                            zj[c] = (double)L.z[c][il][r16];
+                            Ab[c] = (double)acc[c][r];
+                            zd[c] = 0.0;
                         }
+                        bump_d123d(knots[b], L.z[0][il][r16], inv_wd, v);
+                        features_adjoint<double, O0, O1>(v, zj, Ab, zd);
 #pragma unroll
-                        for (int c = 0; c < C; ++c) L.tm[4 * g + r][c][r16] = zc[c];
+                        for (int c = 0; c < C; ++c) L.tm[4 * g + r][c][r16] = e < tot ? (float)zd[c] : 0.f;
                     }
                     __builtin_amdgcn_wave_barrier();
                     // per (channel, point): the block's entries in order, one
@@ -597,7 +599,7 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int il = g + 4 * q;
-                pz[c][q] = (ok && il < nin) ? jet_in<O0, O1, FIRST>(zin, c, i0 + il, win, n, p) : 0.f;
+                pz[c][q] = jet_sel<O0, O1, FIRST>(zin, c, i0 + il, win, n, p, ok && il < nin);
             }
         const int64_t pg = p0_ + 4 * g;
 #pragma unroll

@@ -25,7 +25,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import to_dev
+from gpu_util import gpu_step, to_dev
 from paper_2409_14248_amd import hrkan as H
 from paper_2409_14248_amd import workloads as WL
 
@@ -89,3 +89,58 @@ def test_coordinate_fd_sampled_weights():
             assert abs(d4 - g_k) <= 5e-3 * abs(g_k) + 3e-3 * gmax, (l, int(k), d4, g_k)
             d6 = central(1e-6)
             assert abs(d6 - g_k) <= 1e-5 * abs(g_k) + 1e-5 * gmax, (l, int(k), d6, g_k)
+
+
+@pytest.mark.parametrize("name,n_int,n_bc", [("poisson_c3", 16384, 1024), ("burgers_c4", 8192, 512)])
+def test_directional_fd_of_the_f32_matrix_core_gradient(name, n_int, n_bc):
+    """The FP32 step, whose hidden layers run on the tile-coherent MFMA
+    kernels (forward, input bars through v..v''', weight gradient), against
+    central differences of the FP64 loss of the same FP32-rounded inputs
+    along 8 seeded unit directions V over all layers at once.
+
+    Gate: |FD - <gW32, V>| <= (2e-6 + max(1e-5, 3 floor)) ||gW||, where
+    floor is the whole-gradient error of the oracle's FP32 rounding model on
+    these inputs (|<gW32 - gW, V>| <= ||gW32 - gW|| for a unit V) and 2e-6
+    bounds the central difference's own error, checked first against the
+    FP64 step's gradient on the same directions."""
+    import oracle as O
+    from conftest import check
+    h = 1e-5
+    pr = WL.make_problem(WL.WORKLOADS[name], n_int=n_int, n_bc=n_bc)
+    q = pr.rounded(np.float32)
+    nd = H.net_desc(q.net, "f64")
+    pd = H.pde_desc(q.pde)
+    W = [to_dev(w, "f64") for w in q.W]
+    xi, xb, g = to_dev(q.x_int, "f64"), to_dev(q.x_bc, "f64"), to_dev(q.g_bc, "f64")
+    ws = H.alloc_workspace(H.workspace_bytes(nd, pd, q.n_int, q.n_bc))
+    loss_buf = torch.empty(3, dtype=torch.float64, device="cuda")
+    gW_buf = [torch.empty_like(w) for w in W]
+
+    def loss_at(Wx):
+        H.step(nd, pd, Wx, xi, xb, g, ws, loss_out=loss_buf, gW_out=gW_buf)
+        return float(loss_buf[0].item())
+
+    _, gW64 = H.step(nd, pd, W, xi, xb, g, ws)
+    gW64 = [t.cpu().numpy().copy() for t in gW64]
+    _, gW32, ws32 = gpu_step(q, "f32")
+    assert H.read_status(ws32) == 0
+    ex = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
+    with O.rounding("f32"):
+        md = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
+    gnorm = np.sqrt(sum(float((a * a).sum()) for a in ex["gW"]))
+    floor = np.sqrt(sum(float(((a - b) ** 2).sum()) for a, b in zip(md["gW"], ex["gW"]))) / gnorm
+    tol32 = 2e-6 + max(1e-5, 3.0 * floor)
+    print(f"[fd] {name}: FP32 rounding-model floor {floor:.3e}, gate {tol32:.3e} of ||gW|| = {gnorm:.4e}", flush=True)
+    rng = np.random.default_rng(WL.SEED_BASE + 33)
+    for d in range(8):
+        V = [rng.standard_normal(w.shape) for w in q.W]
+        nrm = np.sqrt(sum(float((v * v).sum()) for v in V))
+        V = [v / nrm for v in V]
+        Vd = [torch.as_tensor(v, device="cuda") for v in V]
+        fd = (loss_at([w + h * v for w, v in zip(W, Vd)]) - loss_at([w - h * v for w, v in zip(W, Vd)])) / (2 * h)
+        a64 = sum(float((a * v).sum()) for a, v in zip(gW64, V))
+        a32 = sum(float((a * v).sum()) for a, v in zip(gW32, V))
+        print(f"[fd] {name} V{d}: FD {fd:+.10e}  FP64 step {a64:+.10e}  FP32 step {a32:+.10e}  "
+              f"|FD-FP32|/||gW|| {abs(fd - a32) / gnorm:.3e}", flush=True)
+        check(f"{name} V{d} FD vs FP64 gradient", abs(fd - a64) / gnorm, 2e-6, literal=True)
+        check(f"{name} V{d} FD vs FP32 MFMA gradient", abs(fd - a32) / gnorm, tol32, literal=True)
