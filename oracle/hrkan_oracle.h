@@ -11,17 +11,21 @@
  *   - the HR basis of order m and its derivatives (Sec. 3, Eq. 2),
  *   - the KAN layer as "basis tensor times weight matrix" (Sec. 3, the
  *     matrix-operation remark; Sec. 2.1-2.2 for the supports),
- *   - forward-mode jets (value, first and second derivative per input
- *     direction) through every layer, as needed by the PDE residuals
- *     (Sec. 4.1 loss, Sec. 4.2 loss),
+ *   - forward-mode jets (value and the derivatives of order 1..n along each
+ *     input direction, n = 2 by default, up to 5) through every layer, as
+ *     needed by the PDE residuals (Sec. 4.1 loss, Sec. 4.2 loss; Sec. 3
+ *     on higher derivatives with a larger m),
  *   - the residuals and the loss L = alpha*L_pde + L_bc (Sec. 4.1 and 4.2),
+ *     and a linear PDE of any order up to n,
  *   - the exact reverse-mode gradient of L with respect to every weight.
  *
- * Jet layout used throughout: five slots per feature,
- *   slot 0 = value, 1 = d/dx0, 2 = d2/dx0^2, 3 = d/dx1, 4 = d2/dx1^2,
+ * Jet layout used throughout, for jet order n (hro_net.order): S = 1 + 2n
+ * slots per feature,
+ *   slot 0 = value, slot k = d^k/dx0^k (k = 1..n), slot n + k = d^k/dx1^k,
  * where x0 is the first input coordinate (x) and x1 the second (y, or t for
- * Burgers). Arrays of jets are [5][width][n] (slot, feature, point), doubles.
- * Slots that a caller does not need are still computed; they cost time only.
+ * Burgers). For n = 2 that is value, d/dx0, d2/dx0^2, d/dx1, d2/dx1^2.
+ * Arrays of jets are [S][width][n] (slot, feature, point), doubles. Slots
+ * that a caller does not need are still computed; they cost time only.
  *
  * Weights of layer l: [w_l * n_b][w_{l+1}] row-major, row index i*n_b + b
  * (input feature i, basis function b), n_b = G + k.
@@ -36,7 +40,8 @@ extern "C" {
 #endif
 
 #define HRO_MAX_LAYERS 8
-#define HRO_SLOTS 5
+#define HRO_MAX_ORDER 5
+#define HRO_MAX_SLOTS (1 + 2 * HRO_MAX_ORDER)
 
 typedef struct {
     int32_t n_layers;                     /* number of KAN layers L          */
@@ -45,16 +50,27 @@ typedef struct {
     int32_t k;                            /* B-spline order of the supports  */
     int32_t m;                            /* HR order                        */
     double lo, hi;                        /* grid range                      */
+    int32_t order;                        /* jet order n, 1..5 (0 means 2)   */
 } hro_net;
 
-enum { HRO_POISSON2D = 0, HRO_BURGERS1D = 1 };
+enum { HRO_POISSON2D = 0, HRO_BURGERS1D = 1, HRO_LINEAR2D = 2 };
 
 typedef struct {
-    int32_t kind;    /* HRO_POISSON2D or HRO_BURGERS1D                        */
+    int32_t kind;    /* HRO_POISSON2D, HRO_BURGERS1D or HRO_LINEAR2D          */
     double nu;       /* Burgers viscosity                                    */
     double alpha;    /* weight of the PDE term in the loss                   */
     double adv;      /* Burgers advection coefficient (1 for u_t+u u_x-nu u_xx) */
+    /* HRO_LINEAR2D: r = c0 u + sum_k cx[k-1] d^k u/dx^k + sum_k cy[k-1]
+     * d^k u/dy^k - f, f the same operator applied to sin(pi x) sin(pi y)
+     * (so that function solves it); every order with a non-zero
+     * coefficient must be at most the jet order. */
+    double c0;
+    double cx[HRO_MAX_ORDER];
+    double cy[HRO_MAX_ORDER];
 } hro_pde;
+
+/* Slots per feature for jet order n: 1 + 2n. */
+int hro_slots(int order);
 
 /* n_b = G + k basis functions per input. */
 int hro_n_basis(const hro_net *net);
@@ -66,46 +82,47 @@ void hro_supports(const hro_net *net, double *s, double *e);
  * written to out[0..nmax]. Zero outside the open interval (s, e). */
 void hro_basis(int m, double s, double e, double z, int nmax, double *out);
 
-/* Teacher-forced layer forward: zin [5][w_l][n] -> zout [5][w_{l+1}][n]. */
+/* Teacher-forced layer forward: zin [S][w_l][n] -> zout [S][w_{l+1}][n]. */
 int hro_layer_forward(const hro_net *net, int layer, const double *W,
                       const double *zin, int64_t n, double *zout);
 
-/* Teacher-forced layer reverse: given the input jets zin [5][w_l][n] and the
- * bars of the output jets ybar [5][w_{l+1}][n], write the bars of the input
- * jets to zbar [5][w_l][n] (may be NULL) and ADD the weight gradient to gW. */
+/* Teacher-forced layer reverse: given the input jets zin [S][w_l][n] and the
+ * bars of the output jets ybar [S][w_{l+1}][n], write the bars of the input
+ * jets to zbar [S][w_l][n] (may be NULL) and ADD the weight gradient to gW. */
 int hro_layer_backward(const hro_net *net, int layer, const double *W,
                        const double *zin, const double *ybar, int64_t n,
                        double *zbar, double *gW);
 
-/* Layer-0 input jets of points x [n][2]: value x, unit first derivative
- * along its own direction, zero second derivatives. zin is [5][2][n]. */
-void hro_input_jets(const double *x, int64_t n, double *zin);
+/* Layer-0 input jets of points x [n][2] for jet order `order`: value x,
+ * unit first derivative along its own direction, every other derivative
+ * zero. zin is [S][2][n]. Returns -1 for an order outside 1..5. */
+int hro_input_jets(const double *x, int64_t n, int order, double *zin);
 
-/* Whole network forward: x [n][2] -> jets of the output u, [5][n].
+/* Whole network forward: x [n][2] -> jets of the output u, [S][n].
  * If all_jets is not NULL it receives the jets entering every layer l = 0..L,
- * concatenated: block l is [5][w_l][n]. */
+ * concatenated: block l is [S][w_l][n]. */
 int hro_forward(const hro_net *net, const double *const *W, const double *x,
                 int64_t n, double *u_jets, double *all_jets);
 
-/* Residual, loss and seeds. jets_int [5][n_int] are the output jets at the
- * interior points x_int [n_int][2]; u_bc [n_bc] are the values at the
- * boundary/initial points with targets g_bc [n_bc].
+/* Residual, loss and seeds. jets_int [S][n_int] (jet order `order`) are the
+ * output jets at the interior points x_int [n_int][2]; u_bc [n_bc] are the
+ * values at the boundary/initial points with targets g_bc [n_bc].
  * loss[0] = L, loss[1] = L_pde, loss[2] = L_bc.
- * r [n_int], seed_int [5][n_int] (dL/d jets) and seed_bc [n_bc] (dL/du) may
- * be NULL. */
-int hro_residual(const hro_pde *pde, const double *x_int,
+ * r [n_int], seed_int [S][n_int] (dL/d jets) and seed_bc [n_bc] (dL/du) may
+ * be NULL. Returns -1 if the PDE needs derivatives above `order`. */
+int hro_residual(const hro_pde *pde, int order, const double *x_int,
                  const double *jets_int, int64_t n_int,
                  const double *u_bc, const double *g_bc, int64_t n_bc,
                  double *r, double *loss, double *seed_int, double *seed_bc);
 
-/* Whole network reverse: given seeds [5][n] on the output jets of points
+/* Whole network reverse: given seeds [S][n] on the output jets of points
  * x [n][2], ADD dL/dW of every layer to gW[l]. */
 int hro_backward(const hro_net *net, const double *const *W, const double *x,
                  int64_t n, const double *seed, double *const *gW);
 
 /* One full step: forward jets at interior and boundary points, residual,
  * loss, and the gradient of L with respect to every weight. gW[l] is
- * OVERWRITTEN. r_out [n_int], jets_out [5][n_int] and ubc_out [n_bc] may be
+ * OVERWRITTEN. r_out [n_int], jets_out [S][n_int] and ubc_out [n_bc] may be
  * NULL. */
 int hro_step(const hro_net *net, const hro_pde *pde, const double *const *W,
              const double *x_int, int64_t n_int,

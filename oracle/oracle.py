@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 CPU-baseline leg of the benchmark. It shares nothing with the GPU library and
 is never a fallback for it.
 
-Jet arrays are [5][width][n] float64 with slots
-(value, d/dx0, d2/dx0^2, d/dx1, d2/dx1^2); the output jets of the network are
-[5][n]. Weights of layer l are [w_l * n_b, w_{l+1}] float64, row i*n_b + b.
+Jet arrays are [S][width][n] float64 with S = 1 + 2n slots for jet order n
+(net.order, 2 unless the net says otherwise): the value, d^k/dx0^k for
+k = 1..n, then d^k/dx1^k; for n = 2 that is (value, d/dx0, d2/dx0^2, d/dx1,
+d2/dx1^2). The output jets of the network are [S][n]. Weights of layer l are
+[w_l * n_b, w_{l+1}] float64, row i*n_b + b.
 """
 from __future__ import annotations
 
@@ -21,9 +23,19 @@ _SRC = os.path.join(_HERE, "hrkan_oracle.c")
 _LIB = os.path.join(_HERE, "libhrkan_oracle.so")
 
 MAX_LAYERS = 8
-SLOTS = 5
+MAX_ORDER = 5
+SLOTS = 5            # slots of the default jet order 2
 POISSON2D = 0
 BURGERS1D = 1
+LINEAR2D = 2
+
+
+def order_of(net) -> int:
+    return int(getattr(net, "order", 2))
+
+
+def slots(order: int) -> int:
+    return 1 + 2 * int(order)
 
 
 def build(force: bool = False) -> str:
@@ -49,6 +61,7 @@ class _Net(ctypes.Structure):
         ("m", ctypes.c_int32),
         ("lo", ctypes.c_double),
         ("hi", ctypes.c_double),
+        ("order", ctypes.c_int32),
     ]
 
 
@@ -58,6 +71,9 @@ class _Pde(ctypes.Structure):
         ("nu", ctypes.c_double),
         ("alpha", ctypes.c_double),
         ("adv", ctypes.c_double),
+        ("c0", ctypes.c_double),
+        ("cx", ctypes.c_double * MAX_ORDER),
+        ("cy", ctypes.c_double * MAX_ORDER),
     ]
 
 
@@ -77,9 +93,9 @@ def _load():
                                   ctypes.c_double, ctypes.c_int, _D]
         lib.hro_layer_forward.argtypes = [P(_Net), ctypes.c_int, _D, _D, i64, _D]
         lib.hro_layer_backward.argtypes = [P(_Net), ctypes.c_int, _D, _D, _D, i64, _D, _D]
-        lib.hro_input_jets.argtypes = [_D, i64, _D]
+        lib.hro_input_jets.argtypes = [_D, i64, ctypes.c_int, _D]
         lib.hro_forward.argtypes = [P(_Net), P(_D), _D, i64, _D, _D]
-        lib.hro_residual.argtypes = [P(_Pde), _D, _D, i64, _D, _D, i64, _D, _D, _D, _D]
+        lib.hro_residual.argtypes = [P(_Pde), ctypes.c_int, _D, _D, i64, _D, _D, i64, _D, _D, _D, _D]
         lib.hro_backward.argtypes = [P(_Net), P(_D), _D, i64, _D, P(_D)]
         lib.hro_step.argtypes = [P(_Net), P(_Pde), P(_D), _D, i64, _D, i64, _D, _D,
                                  P(_D), _D, _D, _D]
@@ -113,6 +129,7 @@ def _net(net) -> _Net:
         n.widths[i] = int(v)
     n.G, n.k, n.m = int(net.G), int(net.k), int(net.m)
     n.lo, n.hi = float(getattr(net, "lo", -1.0)), float(getattr(net, "hi", 1.0))
+    n.order = order_of(net)
     return n
 
 
@@ -122,6 +139,11 @@ def _pde(pde) -> _Pde:
     p.nu = float(pde.nu)
     p.alpha = float(pde.alpha)
     p.adv = float(getattr(pde, "adv", 1.0))
+    p.c0 = float(getattr(pde, "c0", 0.0))
+    for k, v in enumerate(getattr(pde, "cx", ())):
+        p.cx[k] = float(v)
+    for k, v in enumerate(getattr(pde, "cy", ())):
+        p.cy[k] = float(v)
     return p
 
 
@@ -183,11 +205,11 @@ def basis(m: int, s: float, e: float, z: float, nmax: int = 3) -> np.ndarray:
     return out
 
 
-def input_jets(x) -> np.ndarray:
+def input_jets(x, order: int = 2) -> np.ndarray:
     x = _f64(x)
     n = x.shape[0]
-    z = np.zeros((SLOTS, 2, n))
-    _load().hro_input_jets(_ptr(x), n, _ptr(z))
+    z = np.zeros((slots(order), 2, n))
+    assert _load().hro_input_jets(_ptr(x), n, int(order), _ptr(z)) == 0
     return z
 
 
@@ -195,7 +217,7 @@ def layer_forward(net, layer: int, W, zin) -> np.ndarray:
     zin = _f64(zin)
     n = zin.shape[-1]
     wout = list(net.widths)[layer + 1]
-    zout = np.zeros((SLOTS, wout, n))
+    zout = np.zeros((slots(order_of(net)), wout, n))
     nn = _net(net)
     W = _f64(W)
     rc = _load().hro_layer_forward(ctypes.byref(nn), layer, _ptr(W), _ptr(zin), n, _ptr(zout))
@@ -218,15 +240,16 @@ def layer_backward(net, layer: int, W, zin, ybar, want_zbar: bool = True):
 
 
 def forward(net, Ws, x, all_jets: bool = False):
-    """Output jets [5][n]; with all_jets, also the list of per-layer input jets."""
+    """Output jets [S][n]; with all_jets, also the list of per-layer input jets."""
     x = _f64(x)
     n = x.shape[0]
     Ws, arr = _wlist(Ws)
-    u = np.zeros((SLOTS, n))
+    S = slots(order_of(net))
+    u = np.zeros((S, n))
     widths = list(net.widths)
     blocks = None
     if all_jets:
-        tot = sum(SLOTS * w * n for w in widths)
+        tot = sum(S * w * n for w in widths)
         blocks = np.zeros(tot)
     nn = _net(net)
     rc = _load().hro_forward(ctypes.byref(nn), arr, _ptr(x), n, _ptr(u), _ptr(blocks))
@@ -235,24 +258,26 @@ def forward(net, Ws, x, all_jets: bool = False):
         return u
     out, o = [], 0
     for w in widths:
-        out.append(blocks[o:o + SLOTS * w * n].reshape(SLOTS, w, n))
-        o += SLOTS * w * n
+        out.append(blocks[o:o + S * w * n].reshape(S, w, n))
+        o += S * w * n
     return u, out
 
 
-def residual(pde, x_int, jets_int, u_bc, g_bc):
-    """(r [n_int], loss [3], seed_int [5][n_int], seed_bc [n_bc])."""
+def residual(pde, x_int, jets_int, u_bc, g_bc, order: int = 2):
+    """(r [n_int], loss [3], seed_int [S][n_int], seed_bc [n_bc]) for output
+    jets [S][n_int] of jet order `order`."""
     x_int = _f64(x_int)
     jets_int = _f64(jets_int)
     u_bc = _f64(u_bc)
     g_bc = _f64(g_bc)
     ni, nbc = x_int.shape[0], u_bc.shape[0]
+    assert jets_int.shape[0] == slots(order)
     r = np.zeros(ni)
     loss = np.zeros(3)
-    si = np.zeros((SLOTS, ni))
+    si = np.zeros((slots(order), ni))
     sb = np.zeros(nbc)
     p = _pde(pde)
-    rc = _load().hro_residual(ctypes.byref(p), _ptr(x_int), _ptr(jets_int), ni, _ptr(u_bc),
+    rc = _load().hro_residual(ctypes.byref(p), int(order), _ptr(x_int), _ptr(jets_int), ni, _ptr(u_bc),
                               _ptr(g_bc), nbc, _ptr(r), _ptr(loss), _ptr(si), _ptr(sb))
     assert rc == 0
     return r, loss, si, sb
@@ -272,7 +297,7 @@ def backward(net, Ws, x, seed):
 
 
 def step(net, pde, Ws, x_int, x_bc, g_bc):
-    """One full step: dict with loss [3], gW list, r, jets [5][n_int], u_bc."""
+    """One full step: dict with loss [3], gW list, r, jets [S][n_int], u_bc."""
     x_int = _f64(x_int)
     x_bc = _f64(x_bc)
     g_bc = _f64(g_bc)
@@ -282,7 +307,7 @@ def step(net, pde, Ws, x_int, x_bc, g_bc):
     garr = (_D * len(gWs))(*[_ptr(g) for g in gWs])
     loss = np.zeros(3)
     r = np.zeros(ni)
-    jets = np.zeros((SLOTS, ni))
+    jets = np.zeros((slots(order_of(net)), ni))
     ubc = np.zeros(nbc)
     nn = _net(net)
     p = _pde(pde)

@@ -22,6 +22,7 @@ import numpy as np
 
 POISSON2D = 0
 BURGERS1D = 1
+LINEAR2D = 2
 
 SEED_BASE = 2409142480
 
@@ -34,6 +35,7 @@ class Net:
     m: int = 4
     lo: float = -1.0
     hi: float = 1.0
+    order: int = 2        # jet order along each input coordinate
 
     @property
     def n_layers(self) -> int:
@@ -58,6 +60,22 @@ class Pde:
     nu: float = 0.0
     alpha: float = 0.05
     adv: float = 1.0
+    # LINEAR2D: c0 u + sum_k cx[k-1] d^k u/dx^k + sum_k cy[k-1] d^k u/dy^k = f,
+    # f making sin(pi x) sin(pi y) the solution (zero on the square's edges)
+    c0: float = 0.0
+    cx: tuple = ()
+    cy: tuple = ()
+
+    @property
+    def orders(self):
+        """Highest derivative order along x and y that the residual needs."""
+        if self.kind == POISSON2D:
+            return 2, 2
+        if self.kind == BURGERS1D:
+            return 2, 1
+        ox = max([k + 1 for k, c in enumerate(self.cx) if c != 0.0], default=0)
+        oy = max([k + 1 for k, c in enumerate(self.cy) if c != 0.0], default=0)
+        return ox, oy
 
 
 @dataclasses.dataclass
@@ -198,6 +216,17 @@ WORKLOADS = {
     "burgers_paper": Workload("burgers_paper", Net((2, 3, 3, 3, 1), G=7, lo=0.0, hi=2.5),
                               Pde(BURGERS1D, 0.001 / 16.0, adv=0.25), 10000, 300, "f32",
                               SEED_BASE + 6, recipe="burgers_paper"),
+    # fourth derivatives (Sec. 3: larger m for higher derivatives):
+    # u_xxxx + u_yyyy = f on [-1,1]^2, [2,16,16,1], g=8, m=6 (the basis is
+    # C^5, so the gradient's v^(5) is continuous), 8,192 + 4 x 256 points, FP64
+    "linear_o4": Workload("linear_o4", Net((2, 16, 16, 1), G=8, m=6, order=4),
+                          Pde(LINEAR2D, alpha=1e-4, cx=(0, 0, 0, 1), cy=(0, 0, 0, 1)),
+                          8192, 1024, "f64", SEED_BASE + 7),
+    # a fifth derivative, the case Sec. 3 names, with its m = 6:
+    # u_y + u_xxxxx = f on [-1,1]^2, [2,8,8,1], g=6, 4,096 + 4 x 128 points, FP64
+    "linear_o5": Workload("linear_o5", Net((2, 8, 8, 1), G=6, m=6, order=5),
+                          Pde(LINEAR2D, alpha=1e-6, cx=(0, 0, 0, 0, 1), cy=(1,)),
+                          4096, 512, "f64", SEED_BASE + 8),
 }
 
 
@@ -211,7 +240,7 @@ def make_problem(wl: Workload, n_int: Optional[int] = None, n_bc: Optional[int] 
     rx = np.random.default_rng([seed, 2])
     W = weights(wl.net, rw)
     pde = wl.pde if pde is None else pde
-    if pde.kind == POISSON2D:
+    if pde.kind in (POISSON2D, LINEAR2D):
         x_int, x_bc, g = poisson_points(n_int, n_bc, rx, grid=wl.grid_points and n_int == wl.n_int)
     elif wl.recipe == "burgers_paper":
         x_int, x_bc, g = burgers_paper_points(n_int, n_bc, rx)

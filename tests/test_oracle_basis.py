@@ -49,18 +49,24 @@ def exact_hr(m, s, e, z, n):
     return c * poly_eval(p, z)
 
 
-@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_derivatives_match_exact_polynomial(m):
+    """Orders 0..6: the jets of order up to 5 and the adjoint's one more."""
     cases = [(Fraction(-11, 5), Fraction(-3, 5)), (Fraction(1, 5), Fraction(9, 5)),
              (Fraction(-1, 3), Fraction(7, 4))]
     for s, e in cases:
         for frac in (Fraction(1, 7), Fraction(1, 3), Fraction(1, 2), Fraction(5, 8), Fraction(6, 7)):
             z = s + (e - s) * frac
-            got = O.basis(m, float(s), float(e), float(z), 4)
-            for n in range(5):
+            got = O.basis(m, float(s), float(e), float(z), 6)
+            for n in range(7):
                 ref = float(exact_hr(m, s, e, z, n))
-                scale = max(1.0, abs(ref), float((Fraction(2) / (e - s)) ** n))
-                assert abs(got[n] - ref) <= 1e-12 * scale, (m, s, e, z, n, got[n], ref)
+                # the terms of the n-th derivative of the degree-2m polynomial
+                # c_m (e-z)^m (z-s)^m are of size (2/(e-s))^n (2m)!/(2m-n)!
+                # (zero past degree 2m); the sum cancels to zero at odd n on
+                # the midpoint, so the bound is relative to the terms
+                fall = float(np.prod([2 * m - t for t in range(n)])) if n <= 2 * m else 0.0
+                scale = max(1.0, abs(ref), float((Fraction(2) / (e - s)) ** n) * max(fall, 1.0))
+                assert abs(got[n] - ref) <= 1e-13 * scale, (m, s, e, z, n, got[n], ref)
 
 
 @pytest.mark.parametrize("m", [2, 3, 4, 5, 6])
