@@ -267,7 +267,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    C = H.mask_channels(H.pde_mask(pr.pde.kind))
+    C = H.mask_channels(H.pde_mask(pr.pde))
     merged = pr.n_bc > 0 and "fwd_l0_bc" not in prof
     dense = kernel_flops(pr, C, merged=merged)
     live = kernel_flops(pr, C, live=True, merged=merged)

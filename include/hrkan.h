@@ -38,8 +38,10 @@
  *                     contractions run on BF16 matrix cores, see bf16_split).
  *   - Points x are [n][2] row-major: (x, y) for Poisson, (x, t) for Burgers.
  *   - Jets are channel-major [C][n]; the channels present are the set bits of
- *     a channel mask, in the order U, X, XX, Y, YY (X = d/dx0, Y = d/dx1,
- *     where x1 is y for Poisson and t for Burgers).
+ *     a channel mask, in the order U, then the x0-derivatives X, XX, X3, X4,
+ *     X5, then the x1-derivatives Y, YY, Y3, Y4, Y5 (X = d/dx0, Xk =
+ *     d^k/dx0^k, likewise Y; x1 is y for Poisson and t for Burgers). For the
+ *     masks of order at most two that is U, X, XX, Y, YY.
  *   - Weights of layer l are [w_l * n_b][w_{l+1}] row-major, row i*n_b + b for
  *     input feature i and basis function b, 16-byte aligned. Weight gradients
  *     use the same layout, alignment and array type.
@@ -79,13 +81,24 @@ extern "C" {
 /* PDE kinds (hrkan_pde_desc.kind) */
 #define HRKAN_POISSON2D 0   /* u_xx + u_yy = -2 pi^2 sin(pi x) sin(pi y), Sec. 4.1 Eq. 3 */
 #define HRKAN_BURGERS1D 1   /* u_t + adv * u * u_x - nu * u_xx = 0, Sec. 4.2 Eq. 5 / Eq. 6 */
+#define HRKAN_LINEAR2D 2    /* linear, derivatives up to fifth order (Sec. 3's remark on
+                               higher derivatives); see hrkan_pde_desc */
 
-/* jet channels */
+/* jet channels: the value and the derivatives of order 1..5 along each
+ * coordinate (orders above two need HR order m >= 3, and the reverse pass
+ * of order n uses the basis derivative n + 1) */
+#define HRKAN_MAX_ORDER 5
 #define HRKAN_CH_U 1u
 #define HRKAN_CH_X 2u
 #define HRKAN_CH_XX 4u
 #define HRKAN_CH_Y 8u
 #define HRKAN_CH_YY 16u
+#define HRKAN_CH_X3 32u
+#define HRKAN_CH_X4 64u
+#define HRKAN_CH_X5 128u
+#define HRKAN_CH_Y3 256u
+#define HRKAN_CH_Y4 512u
+#define HRKAN_CH_Y5 1024u
 #define HRKAN_MASK_POISSON (HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_XX | HRKAN_CH_Y | HRKAN_CH_YY)
 #define HRKAN_MASK_BURGERS (HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_XX | HRKAN_CH_Y)
 #define HRKAN_MASK_VALUE HRKAN_CH_U
@@ -112,12 +125,21 @@ typedef struct {
 
 /* PDE description (host struct). alpha weighs L_pde in L = alpha L_pde + L_bc
  * (the paper uses 0.05). For Burgers, nu is the viscosity and adv the
- * coefficient of u*u_x (1 for Eq. 5; 1/4 with nu/16 for the rescaled Eq. 6). */
+ * coefficient of u*u_x (1 for Eq. 5; 1/4 with nu/16 for the rescaled Eq. 6).
+ * For HRKAN_LINEAR2D the residual is
+ *   r = c0 u + sum_{k=1..5} cx[k-1] d^k u/dx^k + sum_{k=1..5} cy[k-1] d^k u/dy^k - f,
+ * f being the same operator applied to sin(pi x) sin(pi y), which therefore
+ * solves it (and vanishes on the edges of [-1,1]^2); the interior jets carry
+ * the derivatives up to the highest order with a non-zero coefficient along
+ * each coordinate. */
 typedef struct {
     int32_t kind;
     double nu;
     double alpha;
     double adv;
+    double c0;
+    double cx[HRKAN_MAX_ORDER];
+    double cy[HRKAN_MAX_ORDER];
 } hrkan_pde_desc;
 
 /* Collocation sets (host struct holding device pointers).
@@ -140,9 +162,18 @@ typedef struct {
 int hrkan_net_init(hrkan_net_desc *net);
 int hrkan_pde_init(hrkan_pde_desc *pde, int32_t kind);
 
-/* Number of channels of a mask, or a negative status if the mask is not one
- * of the supported sets (U alone; U,X,XX,Y; U,X,XX,Y,YY; U,X,Y; U,X,XX). */
+/* Number of channels of a mask, or a negative status if it is not a
+ * supported set: it must hold U, and along each coordinate the derivatives
+ * of order 1..o for some o in 0..5 (HRKAN_ERR_INVALID_ARG otherwise). Masks
+ * with an order above two (or the sets U,X; U,Y; U,X,Y,YY; ...) run on the
+ * vector-ALU kernels in FP64 and FP32 only (HRKAN_BF16 is refused with
+ * HRKAN_ERR_UNSUPPORTED); U alone, U,X,Y, U,X,XX, U,X,XX,Y and
+ * U,X,XX,Y,YY also run on the matrix cores. */
 int hrkan_mask_channels(uint32_t channel_mask);
+
+/* The mask of the value and the derivatives of order 1..ox along x0 and
+ * 1..oy along x1 (0 <= ox, oy <= 5), or 0 if an order is out of range. */
+uint32_t hrkan_mask_of_orders(int32_t ox, int32_t oy);
 
 /* Bytes of the `saved` buffer that hrkan_forward_jets fills and
  * hrkan_backward reads for n points: the jets entering layers 1..L-1, in the
@@ -168,7 +199,8 @@ int hrkan_forward_jets(const hrkan_net_desc *net, const void *const *W, const vo
 
 /* Residual, loss and seeds (Sec. 4.1 / 4.2 losses).
  *   jets_int [C][n_int]  output jets at pts->x_int with the PDE's mask
- *                        (HRKAN_MASK_POISSON or HRKAN_MASK_BURGERS)
+ *                        (HRKAN_MASK_POISSON, HRKAN_MASK_BURGERS, or for
+ *                        HRKAN_LINEAR2D the mask of its highest orders)
  *   u_bc     [n_bc]      network values at pts->x_bc
  *   r_out    [n_int]     residual (may be NULL)
  *   loss_out device double[3] = {L, L_pde, L_bc}
@@ -194,7 +226,7 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
 /* One full training step: forward jets at both point sets, residual, loss
  * (loss_out device double[3] = {L, L_pde, L_bc}) and gW_out[l] = dL/dW[l]
  * (overwritten). The interior mask is the PDE's (Poisson: 5 channels,
- * Burgers: 4); only the value enters the boundary loss. Execution depends on
+ * Burgers: 4, linear: up to 11); only the value enters the boundary loss. Execution depends on
  * the set sizes (the results do not, up to rounding): small sets run as one
  * set, medium ones put the boundary set on a second stream that the library
  * creates for `stream` on first use (default priority; every fork is joined

@@ -25,16 +25,23 @@ struct GridP {
 };
 
 // Jet channels of a layer's features, fixed at compile time by the order of
-// differentiation along the two input coordinates: O0 along x0 (0..2) and
-// O1 along x1 (0..2). Channel order: U, X, XX, Y, YY (absent ones skipped).
+// differentiation along the two input coordinates: O0 along x0 and O1 along
+// x1 (0..5 each). Channel order: U, the x0-derivatives of order 1..O0, the
+// x1-derivatives of order 1..O1; for orders up to two U, X, XX, Y, YY
+// (absent ones skipped).
 template <int O0, int O1>
 struct Ch {
     static constexpr int C = 1 + O0 + O1;
+    static constexpr int OM = O0 > O1 ? O0 : O1;      // highest order
+    static constexpr bool LOW = O0 <= 2 && O1 <= 2;    // at most second order
     static constexpr int U = 0;
     static constexpr int X = O0 >= 1 ? 1 : -1;
     static constexpr int XX = O0 >= 2 ? 2 : -1;
     static constexpr int Y = O1 >= 1 ? 1 + O0 : -1;
     static constexpr int YY = O1 >= 2 ? 2 + O0 : -1;
+    // channel of the k-th derivative (k >= 1) along x0 / x1
+    static constexpr int xk(int k) { return k; }
+    static constexpr int yk(int k) { return O0 + k; }
 };
 
 template <typename T>
@@ -109,12 +116,149 @@ __device__ __forceinline__ void hr_bump(const GridP<T> &g, T zeta, int b, T *v)
     }
 }
 
+// HR bump b and its z-derivatives of order 0..ND (ND up to 8) at scaled
+// coordinate zeta. With t = a be and d = be - a as above, t' = d and
+// t'' = -2 in zeta, so (Faa di Bruno for an inner function of degree two)
+//   d^j t^m / dzeta^j = sum_{i=0}^{j/2} j! / (i! (j-2i)!) (-1)^i d^(j-2i)
+//                       * m! / (m-j+i)! * t^(m-j+i),
+// terms with j - i > m being zero; each zeta-derivative is then scaled by
+// inv_w^j. Zero outside the open support; NaN zeta propagates.
+template <typename T, int ND>
+__device__ __forceinline__ void hr_bump_n(const GridP<T> &g, T zeta, int b, T *v)
+{
+    const T a = zeta - T(b - g.k) * g.kappa;
+    const T be = T(b + 1) * g.kappa - zeta;
+    const bool in = (a > T(0)) && (be > T(0)) && b >= 0 && b < g.nb;
+    const T t = a * be;
+    const T d = be - a;
+    const int m = g.m;
+    // powers d^0..d^ND
+    T dp[ND + 1];
+    dp[0] = T(1);
+#pragma unroll
+    for (int e = 1; e <= ND; ++e) dp[e] = dp[e - 1] * d;
+    T sc = T(1);
+#pragma unroll
+    for (int j = 0; j <= ND; ++j) {
+        T sum = T(0);
+        T jf = T(1);                                  // j! / (i! (j-2i)!) by recurrence in i
+#pragma unroll
+        for (int i = 0; 2 * i <= j; ++i) {
+            const int r = j - i;                      // order of the derivative of t^m
+            if (i > 0) jf = jf * T((j - 2 * i + 2) * (j - 2 * i + 1)) / T(i);
+            if (r <= m) {
+                T fall = T(1);                        // m! / (m-r)!
+                for (int q = 0; q < r; ++q) fall *= T(m - q);
+                const T term = jf * dp[j - 2 * i] * fall * ipow(t, m - r);
+                sum += (i & 1) ? -term : term;
+            }
+        }
+        v[j] = in ? sum * sc : T(0);
+        sc *= g.inv_w;
+    }
+    if (!(zeta == zeta))
+#pragma unroll
+        for (int j = 0; j <= ND; ++j) v[j] = zeta;
+}
+
+// Jets of any order along one coordinate through one basis function, in
+// normalised Taylor coefficients: with c_i = z^(i) / i! (i = 1..N) and
+// delta(h) = sum_i c_i h^i, v(z0 + delta) = sum_j v^(j) / j! delta^j, so the
+// k-th derivative of the feature is k! sum_{j=1..k} v^(j) / j! [h^k] delta^j.
+// P[j][k] = [h^k] delta^j, built by repeated truncated products.
+template <typename T, int N>
+__device__ __forceinline__ void taylor_powers(const T *c, T (*P)[N + 1])
+{
+#pragma unroll
+    for (int k = 0; k <= N; ++k) P[0][k] = k == 0 ? T(1) : T(0);
+#pragma unroll
+    for (int j = 1; j <= N; ++j)
+#pragma unroll
+        for (int k = 0; k <= N; ++k) {
+            T s = T(0);
+#pragma unroll
+            for (int i = 1; i <= k; ++i) s += c[i] * P[j - 1][k - i];
+            P[j][k] = s;
+        }
+}
+
+__device__ __forceinline__ constexpr double fact_d(int n) { return n <= 1 ? 1.0 : n * fact_d(n - 1); }
+
+// Features of one coordinate's channels: A[k-1] = d^k/dx^k v(z(x)), k = 1..N,
+// from the derivatives zd[1..N] of z and v[0..N] of the bump.
+template <typename T, int N>
+__device__ __forceinline__ void taylor_features(const T *v, const T *zd, T *A)
+{
+    T c[N + 1];
+    c[0] = T(0);
+#pragma unroll
+    for (int i = 1; i <= N; ++i) c[i] = zd[i] * T(1.0 / fact_d(i));
+    T P[N + 1][N + 1];
+    taylor_powers<T, N>(c, P);
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 1; j <= k; ++j) s += v[j] * T(1.0 / fact_d(j)) * P[j][k];
+        A[k - 1] = s * T(fact_d(k));
+    }
+}
+
+// Reverse of taylor_features: add to *z0b the bar of z (through v^(j+1))
+// and to zdb[i] the bars of z^(i), given the feature bars Ab[k-1]:
+//   dA_k/dz     = k! sum_j v^(j+1) / j! P[j][k],
+//   dA_k/dz^(i) = k! / i! sum_j v^(j) / (j-1)! P[j-1][k-i]   (d[h^k]delta^j/dc_i = j [h^(k-i)]delta^(j-1)).
+template <typename T, int N>
+__device__ __forceinline__ void taylor_adjoint(const T *v, const T *zd, const T *Ab, T *z0b, T *zdb)
+{
+    T c[N + 1];
+    c[0] = T(0);
+#pragma unroll
+    for (int i = 1; i <= N; ++i) c[i] = zd[i] * T(1.0 / fact_d(i));
+    T P[N + 1][N + 1];
+    taylor_powers<T, N>(c, P);
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        const T ab = Ab[k - 1] * T(fact_d(k));
+        T dz = T(0);
+#pragma unroll
+        for (int j = 1; j <= k; ++j) dz += v[j + 1] * T(1.0 / fact_d(j)) * P[j][k];
+        *z0b += ab * dz;
+#pragma unroll
+        for (int i = 1; i <= k; ++i) {
+            T di = T(0);
+#pragma unroll
+            for (int j = 1; j <= k - i + 1; ++j) di += v[j] * T(1.0 / fact_d(j - 1)) * P[j - 1][k - i];
+            zdb[i] += ab * T(1.0 / fact_d(i)) * di;
+        }
+    }
+}
+
 // Features of one basis function for one point, per channel:
 //   A_U = v, A_X = v' zx, A_XX = v'' zx^2 + v' zxx, A_Y = v' zy, A_YY = v'' zy^2 + v' zyy
 template <typename T, int O0, int O1>
 __device__ __forceinline__ void features(const T *v, const T *zj, T *A)
 {
     using CH = Ch<O0, O1>;
+    if constexpr (!CH::LOW) {
+        // any order: v[0..OM] (hr_bump_n), per coordinate in Taylor form
+        A[CH::U] = v[0];
+        if constexpr (O0 > 0) {
+            T zd[O0 + 1];
+            zd[0] = T(0);
+#pragma unroll
+            for (int k = 1; k <= O0; ++k) zd[k] = zj[CH::xk(k)];
+            taylor_features<T, O0>(v, zd, A + CH::xk(1));
+        }
+        if constexpr (O1 > 0) {
+            T zd[O1 + 1];
+            zd[0] = T(0);
+#pragma unroll
+            for (int k = 1; k <= O1; ++k) zd[k] = zj[CH::yk(k)];
+            taylor_features<T, O1>(v, zd, A + CH::yk(1));
+        }
+        return;
+    }
     A[CH::U] = v[0];
     if constexpr (CH::X >= 0) A[CH::X] = v[1] * zj[CH::X];
     if constexpr (CH::XX >= 0) A[CH::XX] = v[2] * zj[CH::X] * zj[CH::X] + v[1] * zj[CH::XX];
@@ -128,6 +272,34 @@ template <typename T, int O0, int O1>
 __device__ __forceinline__ void features_adjoint(const T *v, const T *zj, const T *Ab, T *zb)
 {
     using CH = Ch<O0, O1>;
+    if constexpr (!CH::LOW) {
+        // any order: v[0..OM+1] (hr_bump_n)
+        T z0 = Ab[CH::U] * v[1];
+        if constexpr (O0 > 0) {
+            T zd[O0 + 1], zdb[O0 + 1];
+#pragma unroll
+            for (int k = 0; k <= O0; ++k) {
+                zd[k] = k == 0 ? T(0) : zj[CH::xk(k)];
+                zdb[k] = T(0);
+            }
+            taylor_adjoint<T, O0>(v, zd, Ab + CH::xk(1), &z0, zdb);
+#pragma unroll
+            for (int k = 1; k <= O0; ++k) zb[CH::xk(k)] += zdb[k];
+        }
+        if constexpr (O1 > 0) {
+            T zd[O1 + 1], zdb[O1 + 1];
+#pragma unroll
+            for (int k = 0; k <= O1; ++k) {
+                zd[k] = k == 0 ? T(0) : zj[CH::yk(k)];
+                zdb[k] = T(0);
+            }
+            taylor_adjoint<T, O1>(v, zd, Ab + CH::yk(1), &z0, zdb);
+#pragma unroll
+            for (int k = 1; k <= O1; ++k) zb[CH::yk(k)] += zdb[k];
+        }
+        zb[CH::U] += z0;
+        return;
+    }
     T z0 = Ab[CH::U] * v[1];
     if constexpr (CH::X >= 0) {
         z0 += Ab[CH::X] * v[2] * zj[CH::X];
@@ -156,6 +328,14 @@ template <typename T, int O0, int O1>
 __device__ __forceinline__ void input_jets(const T *x, int64_t p, int i, T *zj)
 {
     using CH = Ch<O0, O1>;
+    if constexpr (!CH::LOW) {
+#pragma unroll
+        for (int c = 0; c < CH::C; ++c) zj[c] = T(0);
+        zj[CH::U] = x[2 * p + i];
+        if constexpr (O0 > 0) zj[CH::xk(1)] = i == 0 ? T(1) : T(0);
+        if constexpr (O1 > 0) zj[CH::yk(1)] = i == 1 ? T(1) : T(0);
+        return;
+    }
     zj[CH::U] = x[2 * p + i];
     if constexpr (CH::X >= 0) zj[CH::X] = i == 0 ? T(1) : T(0);
     if constexpr (CH::XX >= 0) zj[CH::XX] = T(0);

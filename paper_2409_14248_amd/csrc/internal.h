@@ -90,6 +90,8 @@ hipError_t launch_adam(AdamTable<T> tab, int64_t *tdev, double lr, double b1, do
 struct PdeParams {
     int kind;
     double nu, alpha, adv;
+    double c0, cx[HRKAN_MAX_ORDER], cy[HRKAN_MAX_ORDER];   // HRKAN_LINEAR2D
+    int ox, oy;                                            // its jet orders
 };
 template <typename T>
 hipError_t launch_residual(const PdeParams &pde, int C, const T *jets, const T *x_int,

@@ -1,349 +1,9 @@
-// kernels_generic.hip -- vector-ALU kernels of the HRKAN step for any array
-// type T (double or float): one KAN layer forward with jets, its reverse to
-// the input jets, its weight gradient, and the residual / loss kernels.
-//
-// Only the k+1 basis functions whose support contains z are evaluated (the
-// others are zero by the ReLU factors of Eq. 2); their values are staged in
-// LDS once per (point, input) and reused by every output column.
-//
-// Jet arrays are [C][w][n] (channel, feature, point): consecutive threads
-// touch consecutive points.
-#include "internal.h"
+// kernels_generic.hip -- the FP32 instances of the vector-ALU layer kernels
+// (generic_layers.h), and the reduction, Adam, residual and loss kernels of
+// the HRKAN step for both array types.
+#include "generic_layers.h"
 
 namespace hrk {
-
-constexpr int NT = 256;      // threads per block
-constexpr int TP = 64;       // points per block (forward, input bars)
-constexpr int KBMAX = 4;     // at most k+1 = 4 live basis functions per input
-constexpr int NBMAX = 32;    // n_b limit of the weight-gradient kernel
-constexpr int NOQ = -(1 << 20);
-
-#define HRK_CH_SWITCH(ch, ...)                                   \
-    switch ((ch).o0 * 3 + (ch).o1) {                              \
-    case 0: { constexpr int O0 = 0, O1 = 0; __VA_ARGS__; } break;        \
-    case 4: { constexpr int O0 = 1, O1 = 1; __VA_ARGS__; } break;        \
-    case 6: { constexpr int O0 = 2, O1 = 0; __VA_ARGS__; } break;        \
-    case 7: { constexpr int O0 = 2, O1 = 1; __VA_ARGS__; } break;        \
-    case 8: { constexpr int O0 = 2, O1 = 2; __VA_ARGS__; } break;        \
-    default: return hipErrorInvalidValue;                         \
-    }
-
-// Load the jets of input feature i at point p (layer 0 reads x directly).
-template <typename T, int O0, int O1, bool FIRST>
-__device__ __forceinline__ void load_jets(const T *__restrict__ zin, int64_t n, int win, int i,
-                                          int64_t p, T *zj)
-{
-    constexpr int C = Ch<O0, O1>::C;
-    if constexpr (FIRST) {
-        input_jets<T, O0, O1>(zin, p, i, zj);
-    } else {
-#pragma unroll
-        for (int c = 0; c < C; ++c) zj[c] = zin[((int64_t)c * win + i) * n + p];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// forward: zout[c][j][p] = sum_i sum_b W[i*nb+b][j] * A_c(p, i, b)
-// grid (ceil(n/64), ceil(N/32)); each thread owns one point and 8 outputs.
-// ---------------------------------------------------------------------------
-template <typename T, int O0, int O1, bool FIRST>
-__global__ __launch_bounds__(NT) void k_fwd_generic(const T *__restrict__ zin,
-                                                    const T *__restrict__ W,
-                                                    T *__restrict__ zout, int64_t n, int win,
-                                                    int N, GridP<T> g)
-{
-    constexpr int C = Ch<O0, O1>::C;
-    constexpr int KI = 8;                 // inputs staged per pass
-    constexpr int JS = NT / TP;           // output sub-columns per point
-    constexpr int NJ = 8;                 // outputs per thread
-    __shared__ int sq[KI][TP];
-    __shared__ T sA[KI][KBMAX][C][TP];
-
-    const int tid = threadIdx.x, tp = tid % TP, js = tid / TP;
-    const int64_t p0 = (int64_t)blockIdx.x * TP;
-    const int j0 = blockIdx.y * (NJ * JS);
-    const int kb = g.k + 1;
-    T acc[NJ][C];
-#pragma unroll
-    for (int r = 0; r < NJ; ++r)
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[r][c] = T(0);
-
-    for (int i0 = 0; i0 < win; i0 += KI) {
-        for (int it = tid; it < KI * TP; it += NT) {
-            const int il = it / TP, pp = it % TP, i = i0 + il;
-            const int64_t p = p0 + pp;
-            T zj[C];
-            T zt = T(0);
-            int q = NOQ;
-            if (i < win && p < n) {
-                load_jets<T, O0, O1, FIRST>(zin, n, win, i, p, zj);
-                zt = zeta_of(g, zj[0]);
-                q = interval_of(g, zt);
-            }
-            sq[il][pp] = q;
-#pragma unroll
-            for (int t = 0; t < KBMAX; ++t) {
-                T A[C];
-                if (t < kb && q != NOQ) {
-                    T v[3];
-                    hr_bump<T, 2>(g, zt, q + t, v);
-                    features<T, O0, O1>(v, zj, A);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) A[c] = T(0);
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) sA[il][t][c][pp] = A[c];
-            }
-        }
-        __syncthreads();
-        const int ilmax = min(KI, win - i0);
-        for (int il = 0; il < ilmax; ++il) {
-            const int q = sq[il][tp];
-#pragma unroll
-            for (int t = 0; t < KBMAX; ++t) {
-                const int b = q + t;
-                if (t >= kb || b < 0 || b >= g.nb) continue;
-                const T *wr = W + (size_t)((i0 + il) * g.nb + b) * N;
-                T a[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) a[c] = sA[il][t][c][tp];
-#pragma unroll
-                for (int r = 0; r < NJ; ++r) {
-                    const int j = j0 + js + JS * r;
-                    if (j < N) {
-                        const T w = wr[j];
-#pragma unroll
-                        for (int c = 0; c < C; ++c) acc[r][c] += a[c] * w;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    const int64_t p = p0 + tp;
-    if (p < n) {
-#pragma unroll
-        for (int r = 0; r < NJ; ++r) {
-            const int j = j0 + js + JS * r;
-            if (j < N)
-#pragma unroll
-                for (int c = 0; c < C; ++c) zout[((int64_t)c * N + j) * n + p] = acc[r][c];
-        }
-    }
-}
-
-template <typename T>
-hipError_t launch_fwd_generic(ChanCfg ch, bool first, const T *zin, const T *W, T *zout,
-                              int64_t n, LayerShape ls, const GridP<T> &g, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + TP - 1) / TP), (unsigned)((ls.wout + 31) / 32));
-    HRK_CH_SWITCH(ch, {
-        if (first)
-            k_fwd_generic<T, O0, O1, true><<<grid, NT, 0, st>>>(zin, W, zout, n, ls.win, ls.wout, g);
-        else
-            k_fwd_generic<T, O0, O1, false><<<grid, NT, 0, st>>>(zin, W, zout, n, ls.win, ls.wout, g);
-    });
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// reverse to the input jets:
-//   Ab_c(p,i,b) = sum_j W[i*nb+b][j] * ybar[c][j][p]   (live b only)
-//   zbar[.][i][p] = adjoint of the features through v, v', v'', v'''
-// grid (ceil(n/64), ceil(win/8)); each thread owns one point and 2 inputs.
-// ---------------------------------------------------------------------------
-template <typename T, int O0, int O1>
-__global__ __launch_bounds__(NT) void k_dx_generic(const T *__restrict__ zin,
-                                                   const T *__restrict__ ybar,
-                                                   const T *__restrict__ W,
-                                                   T *__restrict__ zbar, int64_t n, int win,
-                                                   int N, GridP<T> g)
-{
-    constexpr int C = Ch<O0, O1>::C;
-    constexpr int RI = 2;
-    constexpr int IS = NT / TP;
-    constexpr int JC = 32;
-    __shared__ T sY[C][JC][TP];
-
-    const int tid = threadIdx.x, tp = tid % TP, ig = tid / TP;
-    const int64_t p0 = (int64_t)blockIdx.x * TP, p = p0 + tp;
-    const int ib = blockIdx.y * (RI * IS);
-    const int kb = g.k + 1;
-    T zj[RI][C];
-    T zt[RI];
-    int q[RI];
-    T Ab[RI][KBMAX][C];
-#pragma unroll
-    for (int r = 0; r < RI; ++r) {
-        const int i = ib + ig + IS * r;
-        q[r] = NOQ;
-        zt[r] = T(0);
-#pragma unroll
-        for (int c = 0; c < C; ++c) zj[r][c] = T(0);
-        if (i < win && p < n) {
-            load_jets<T, O0, O1, false>(zin, n, win, i, p, zj[r]);
-            zt[r] = zeta_of(g, zj[r][0]);
-            q[r] = interval_of(g, zt[r]);
-        }
-#pragma unroll
-        for (int t = 0; t < KBMAX; ++t)
-#pragma unroll
-            for (int c = 0; c < C; ++c) Ab[r][t][c] = T(0);
-    }
-    for (int j0 = 0; j0 < N; j0 += JC) {
-        for (int it = tid; it < C * JC * TP; it += NT) {
-            const int c = it / (JC * TP), rem = it % (JC * TP), jj = rem / TP, pp = rem % TP;
-            const int j = j0 + jj;
-            const int64_t pq = p0 + pp;
-            sY[c][jj][pp] = (j < N && pq < n) ? ybar[((int64_t)c * N + j) * n + pq] : T(0);
-        }
-        __syncthreads();
-        const int jmax = min(JC, N - j0);
-        for (int jj = 0; jj < jmax; ++jj) {
-            T y[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) y[c] = sY[c][jj][tp];
-#pragma unroll
-            for (int r = 0; r < RI; ++r) {
-                const int i = ib + ig + IS * r;
-#pragma unroll
-                for (int t = 0; t < KBMAX; ++t) {
-                    const int b = q[r] + t;
-                    if (t >= kb || b < 0 || b >= g.nb) continue;
-                    const T w = W[(size_t)(i * g.nb + b) * N + j0 + jj];
-#pragma unroll
-                    for (int c = 0; c < C; ++c) Ab[r][t][c] += w * y[c];
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < RI; ++r) {
-        const int i = ib + ig + IS * r;
-        if (i >= win || p >= n) continue;
-        T zb[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) zb[c] = T(0);
-#pragma unroll
-        for (int t = 0; t < KBMAX; ++t) {
-            if (t >= kb) continue;
-            T v[4];
-            hr_bump<T, 3>(g, zt[r], q[r] + t, v);
-            features_adjoint<T, O0, O1>(v, zj[r], Ab[r][t], zb);
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) zbar[((int64_t)c * win + i) * n + p] = zb[c];
-    }
-}
-
-template <typename T>
-hipError_t launch_dx_generic(ChanCfg ch, const T *zin, const T *ybar, const T *W, T *zbar,
-                             int64_t n, LayerShape ls, const GridP<T> &g, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + TP - 1) / TP), (unsigned)((ls.win + 7) / 8));
-    HRK_CH_SWITCH(ch, {
-        k_dx_generic<T, O0, O1><<<grid, NT, 0, st>>>(zin, ybar, W, zbar, n, ls.win, ls.wout, g);
-    });
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// weight gradient of one point slice:
-//   part[s][(i*nb+b)*N + j] = sum_{p in slice s} sum_c A_c(p,i,b) * ybar[c][j][p]
-// grid (ceil(win/8), ceil(N/32), nsplit); the block accumulates its
-// 8 x nb x 32 tile in LDS, each (i, j) column owned by one thread, so the
-// sum over points has a fixed order.
-// ---------------------------------------------------------------------------
-constexpr int DW_IB = 8, DW_JB = 32, DW_TP = 32;
-
-template <typename T, int O0, int O1, bool FIRST>
-__global__ __launch_bounds__(NT) void k_dw_generic(const T *__restrict__ zin,
-                                                   const T *__restrict__ ybar,
-                                                   T *__restrict__ part, int64_t n, int win,
-                                                   int N, int nsplit, GridP<T> g)
-{
-    constexpr int C = Ch<O0, O1>::C;
-    __shared__ T gacc[DW_IB * NBMAX * DW_JB];
-    __shared__ int sq[DW_IB][DW_TP];
-    __shared__ T sA[DW_IB][KBMAX][C][DW_TP];
-    __shared__ T sY[C][DW_JB][DW_TP + 1];
-
-    const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * DW_IB, j0 = blockIdx.y * DW_JB, split = blockIdx.z;
-    const int nb = g.nb, kb = g.k + 1;
-    const int64_t per = ((n + nsplit - 1) / nsplit + DW_TP - 1) / DW_TP * DW_TP;
-    const int64_t ps = (int64_t)split * per;
-    const int64_t pe = min(n, ps + per);
-    for (int it = tid; it < DW_IB * nb * DW_JB; it += NT) gacc[it] = T(0);
-    const int il = tid / DW_JB, jj = tid % DW_JB;
-
-    for (int64_t pc = ps; pc < pe; pc += DW_TP) {
-        for (int it = tid; it < DW_IB * DW_TP; it += NT) {
-            const int il2 = it / DW_TP, pp = it % DW_TP, i = i0 + il2;
-            const int64_t p = pc + pp;
-            T zj[C];
-            T zt = T(0);
-            int q = NOQ;
-            if (i < win && p < pe) {
-                load_jets<T, O0, O1, FIRST>(zin, n, win, i, p, zj);
-                zt = zeta_of(g, zj[0]);
-                q = interval_of(g, zt);
-            }
-            sq[il2][pp] = q;
-#pragma unroll
-            for (int t = 0; t < KBMAX; ++t) {
-                T A[C];
-                if (t < kb && q != NOQ) {
-                    T v[3];
-                    hr_bump<T, 2>(g, zt, q + t, v);
-                    features<T, O0, O1>(v, zj, A);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) A[c] = T(0);
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c) sA[il2][t][c][pp] = A[c];
-            }
-        }
-        for (int it = tid; it < C * DW_JB * DW_TP; it += NT) {
-            const int c = it / (DW_JB * DW_TP), rem = it % (DW_JB * DW_TP);
-            const int j2 = rem / DW_TP, pp = rem % DW_TP;
-            const int j = j0 + j2;
-            const int64_t p = pc + pp;
-            sY[c][j2][pp] = (j < N && p < pe) ? ybar[((int64_t)c * N + j) * n + p] : T(0);
-        }
-        __syncthreads();
-        for (int pp = 0; pp < DW_TP; ++pp) {
-            const int q = sq[il][pp];
-            if (q == NOQ) continue;
-            T y[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) y[c] = sY[c][jj][pp];
-#pragma unroll
-            for (int t = 0; t < KBMAX; ++t) {
-                const int b = q + t;
-                if (t >= kb || b < 0 || b >= nb) continue;
-                T s = T(0);
-#pragma unroll
-                for (int c = 0; c < C; ++c) s += sA[il][t][c][pp] * y[c];
-                gacc[(il * nb + b) * DW_JB + jj] += s;
-            }
-        }
-        __syncthreads();
-    }
-    const int64_t KN = (int64_t)win * nb * N;
-    for (int it = tid; it < DW_IB * nb * DW_JB; it += NT) {
-        const int il2 = it / (nb * DW_JB), rem = it % (nb * DW_JB), b = rem / DW_JB,
-                  j2 = rem % DW_JB;
-        const int i = i0 + il2, j = j0 + j2;
-        if (i < win && j < N) part[split * KN + (int64_t)(i * nb + b) * N + j] = gacc[it];
-    }
-}
 
 int dw_generic_splits(int64_t n, LayerShape ls)
 {
@@ -359,26 +19,11 @@ int dw_generic_splits(int64_t n, LayerShape ls)
 size_t dw_generic_lds_bytes(int elem, int C, int nb)
 {
     (void)nb;
-    return (size_t)elem * (DW_IB * NBMAX * DW_JB + DW_IB * KBMAX * C * DW_TP + C * DW_JB * (DW_TP + 1)) +
-           sizeof(int) * DW_IB * DW_TP;
+    const int tp = C > 5 ? 8 : DW_TP;
+    return (size_t)elem * (DW_IB * NBMAX * DW_JB + DW_IB * KBMAX * C * tp + C * DW_JB * (tp + 1)) +
+           sizeof(int) * DW_IB * tp;
 }
 
-template <typename T>
-hipError_t launch_dw_generic(ChanCfg ch, bool first, const T *zin, const T *ybar, T *part,
-                             int nsplit, int64_t n, LayerShape ls, const GridP<T> &g,
-                             hipStream_t st)
-{
-    if (ls.nb > NBMAX || g.k + 1 > KBMAX) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((ls.win + DW_IB - 1) / DW_IB), (unsigned)((ls.wout + DW_JB - 1) / DW_JB),
-              (unsigned)nsplit);
-    HRK_CH_SWITCH(ch, {
-        if (first)
-            k_dw_generic<T, O0, O1, true><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, ls.wout, nsplit, g);
-        else
-            k_dw_generic<T, O0, O1, false><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, ls.wout, nsplit, g);
-    });
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // out[e] (+)= sum over slices. A block takes 32 elements; its 8 slice lanes
@@ -535,6 +180,67 @@ hipError_t launch_reduce_layers(ReduceTable<T> tab, int accumulate, hipStream_t 
 template <typename T> __device__ __forceinline__ T sin_pi(T v);
 template <> __device__ __forceinline__ double sin_pi<double>(double v) { return sinpi(v); }
 template <> __device__ __forceinline__ float sin_pi<float>(float v) { return sinpif(v); }
+template <typename T> __device__ __forceinline__ T cos_pi(T v);
+template <> __device__ __forceinline__ double cos_pi<double>(double v) { return cospi(v); }
+template <> __device__ __forceinline__ float cos_pi<float>(float v) { return cospif(v); }
+
+// Coefficients of the PDE in the array type.
+template <typename T>
+struct PdeK {
+    T nu, adv;
+    T c0, cx[HRKAN_MAX_ORDER], cy[HRKAN_MAX_ORDER];   // linear kind
+    int ox, oy;                                        // its jet orders
+};
+
+template <typename T>
+PdeK<T> pde_k(const PdeParams &p)
+{
+    PdeK<T> k{};
+    k.nu = (T)p.nu;
+    k.adv = (T)p.adv;
+    k.c0 = (T)p.c0;
+    for (int i = 0; i < HRKAN_MAX_ORDER; ++i) {
+        k.cx[i] = (T)p.cx[i];
+        k.cy[i] = (T)p.cy[i];
+    }
+    k.ox = p.ox;
+    k.oy = p.oy;
+    return k;
+}
+
+// d^k/dt^k sin(pi t) = pi^k times sin, cos, -sin, -cos (pi t) for k mod 4 =
+// 0, 1, 2, 3, from s = sin(pi t), c = cos(pi t).
+template <typename T>
+__device__ __forceinline__ T dsin_pi(int k, T s, T c)
+{
+    T pk = T(1);
+    for (int i = 0; i < k; ++i) pk *= T(3.14159265358979323846);
+    const T v = (k & 1) ? c : s;
+    return (k & 2) ? -pk * v : pk * v;
+}
+
+// Residual of the linear kind at one point and its seeds: r is the operator
+// applied to u minus the operator applied to u* = sin(pi x) sin(pi y),
+// channel by channel; the seed of a channel is rho times its coefficient.
+// jets/seed are [C][stride] with C = 1 + ox + oy.
+template <typename T>
+__device__ __forceinline__ T linear_residual(const PdeK<T> &k, const T *__restrict__ jets, int64_t stride, int64_t p,
+                                             T x, T y)
+{
+    const T sx = sin_pi(x), sy = sin_pi(y), cx = cos_pi(x), cy = cos_pi(y);
+    T r = k.c0 * (jets[p] - sx * sy);
+    for (int q = 1; q <= k.ox; ++q) r += k.cx[q - 1] * (jets[q * stride + p] - dsin_pi(q, sx, cx) * sy);
+    for (int q = 1; q <= k.oy; ++q) r += k.cy[q - 1] * (jets[(k.ox + q) * stride + p] - sx * dsin_pi(q, sy, cy));
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void linear_seed(const PdeK<T> &k, T rho, T *__restrict__ seed, int64_t stride, int64_t p)
+{
+    seed[p] = rho * k.c0;
+    for (int q = 1; q <= k.ox; ++q) seed[q * stride + p] = rho * k.cx[q - 1];
+    for (int q = 1; q <= k.oy; ++q) seed[(k.ox + q) * stride + p] = rho * k.cy[q - 1];
+}
 
 // Points 0..n_int-1 are interior (residual), n_int..n_int+n_bc-1 boundary.
 template <typename T, int KIND>
@@ -544,9 +250,10 @@ __global__ __launch_bounds__(NT) void k_residual(const T *__restrict__ jets,
                                                  const T *__restrict__ g_bc, int64_t n_bc,
                                                  T *__restrict__ r_out, T *__restrict__ seed_int,
                                                  T *__restrict__ seed_bc,
-                                                 double *__restrict__ partials, T alpha, T nu,
-                                                 T adv, T sc_int, T sc_bc)
+                                                 double *__restrict__ partials, PdeK<T> pk,
+                                                 T sc_int, T sc_bc)
 {
+    const T nu = pk.nu, adv = pk.adv;
     __shared__ double sh[4];
     const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
     double e_pde = 0.0, e_bc = 0.0;
@@ -566,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_residual(const T *__restrict__ jets,
                 seed_int[3 * n_int + p] = T(0);
                 seed_int[4 * n_int + p] = rho;
             }
-        } else {
+        } else if constexpr (KIND == 1) {
             // Burgers: jets (u, ux, uxx, ut); r = ut + adv u ux - nu uxx
             const T u = jets[p], ux = jets[n_int + p], uxx = jets[2 * n_int + p],
                     ut = jets[3 * n_int + p];
@@ -578,6 +285,10 @@ __global__ __launch_bounds__(NT) void k_residual(const T *__restrict__ jets,
                 seed_int[2 * n_int + p] = -rho * nu;
                 seed_int[3 * n_int + p] = rho;
             }
+        } else {
+            // linear, jets (u, x-derivatives 1..ox, y-derivatives 1..oy)
+            r = linear_residual(pk, jets, n_int, p, x_int[2 * p], x_int[2 * p + 1]);
+            if (seed_int) linear_seed(pk, sc_int * r, seed_int, n_int, p);
         }
         if (r_out) r_out[p] = r;
         e_pde = (double)r * (double)r;
@@ -593,7 +304,6 @@ __global__ __launch_bounds__(NT) void k_residual(const T *__restrict__ jets,
         partials[2 * blockIdx.x] = s0;
         partials[2 * blockIdx.x + 1] = s1;
     }
-    (void)alpha;
 }
 
 int residual_blocks(int64_t n_int, int64_t n_bc)
@@ -612,14 +322,16 @@ hipError_t launch_residual(const PdeParams &pde, int C, const T *jets, const T *
     (void)C;
     const T sc_int = n_int > 0 ? (T)(2.0 * pde.alpha / (double)n_int) : T(0);
     const T sc_bc = n_bc > 0 ? (T)(2.0 / (double)n_bc) : T(0);
-    if (pde.kind == 0)
+    const PdeK<T> pk = pde_k<T>(pde);
+    if (pde.kind == HRKAN_POISSON2D)
         k_residual<T, 0><<<nblk, NT, 0, st>>>(jets, x_int, n_int, u_bc, g_bc, n_bc, r_out, seed_int,
-                                              seed_bc, partials, (T)pde.alpha, (T)pde.nu,
-                                              (T)pde.adv, sc_int, sc_bc);
-    else
+                                              seed_bc, partials, pk, sc_int, sc_bc);
+    else if (pde.kind == HRKAN_BURGERS1D)
         k_residual<T, 1><<<nblk, NT, 0, st>>>(jets, x_int, n_int, u_bc, g_bc, n_bc, r_out, seed_int,
-                                              seed_bc, partials, (T)pde.alpha, (T)pde.nu,
-                                              (T)pde.adv, sc_int, sc_bc);
+                                              seed_bc, partials, pk, sc_int, sc_bc);
+    else
+        k_residual<T, 2><<<nblk, NT, 0, st>>>(jets, x_int, n_int, u_bc, g_bc, n_bc, r_out, seed_int,
+                                              seed_bc, partials, pk, sc_int, sc_bc);
     return hipGetLastError();
 }
 
@@ -667,9 +379,10 @@ __global__ __launch_bounds__(NT) void k_residual_merged(const T *__restrict__ je
                                                         const T *__restrict__ x_int, int64_t n_int,
                                                         const T *__restrict__ g_bc, int64_t n_bc, int C,
                                                         T *__restrict__ seed,
-                                                        double *__restrict__ partials, T nu, T adv,
+                                                        double *__restrict__ partials, PdeK<T> pk,
                                                         T sc_int, T sc_bc)
 {
+    const T nu = pk.nu, adv = pk.adv;
     __shared__ double sh[4];
     const int64_t ns = n_int + n_bc;
     const int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -687,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_residual_merged(const T *__restrict__ je
             seed[2 * ns + p] = rho;
             seed[3 * ns + p] = T(0);
             seed[4 * ns + p] = rho;
-        } else {
+        } else if constexpr (KIND == 1) {
             const T u = jets[p], ux = jets[ns + p], uxx = jets[2 * ns + p], ut = jets[3 * ns + p];
             r = ut + adv * u * ux - nu * uxx;
             const T rho = sc_int * r;
@@ -695,6 +408,9 @@ __global__ __launch_bounds__(NT) void k_residual_merged(const T *__restrict__ je
             seed[1 * ns + p] = rho * adv * u;
             seed[2 * ns + p] = -rho * nu;
             seed[3 * ns + p] = rho;
+        } else {
+            r = linear_residual(pk, jets, ns, p, x_int[2 * p], x_int[2 * p + 1]);
+            linear_seed(pk, sc_int * r, seed, ns, p);
         }
         e_pde = (double)r * (double)r;
     } else if (p < ns) {
@@ -718,12 +434,16 @@ hipError_t launch_residual_merged(const PdeParams &pde, int C, const T *jets, co
 {
     const T sc_int = n_int > 0 ? (T)(2.0 * pde.alpha / (double)n_int) : T(0);
     const T sc_bc = n_bc > 0 ? (T)(2.0 / (double)n_bc) : T(0);
-    if (pde.kind == 0)
-        k_residual_merged<T, 0><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials,
-                                                     (T)pde.nu, (T)pde.adv, sc_int, sc_bc);
+    const PdeK<T> pk = pde_k<T>(pde);
+    if (pde.kind == HRKAN_POISSON2D)
+        k_residual_merged<T, 0><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials, pk,
+                                                     sc_int, sc_bc);
+    else if (pde.kind == HRKAN_BURGERS1D)
+        k_residual_merged<T, 1><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials, pk,
+                                                     sc_int, sc_bc);
     else
-        k_residual_merged<T, 1><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials,
-                                                     (T)pde.nu, (T)pde.adv, sc_int, sc_bc);
+        k_residual_merged<T, 2><<<nblk, NT, 0, st>>>(jets, x_int, n_int, g_bc, n_bc, C, seed, partials, pk,
+                                                     sc_int, sc_bc);
     return hipGetLastError();
 }
 
@@ -736,13 +456,14 @@ hipError_t launch_loss_final(const double *partials, int nblk, int64_t n_int, in
 }
 
 // explicit instantiations
+template hipError_t launch_fwd_generic<float>(ChanCfg, bool, const float *, const float *, float *, int64_t,
+                                              LayerShape, const GridP<float> &, hipStream_t);
+template hipError_t launch_dx_generic<float>(ChanCfg, const float *, const float *, const float *, float *,
+                                             int64_t, LayerShape, const GridP<float> &, hipStream_t);
+template hipError_t launch_dw_generic<float>(ChanCfg, bool, const float *, const float *, float *, int,
+                                             int64_t, LayerShape, const GridP<float> &, hipStream_t);
+
 #define HRK_INST(T)                                                                              \
-    template hipError_t launch_fwd_generic<T>(ChanCfg, bool, const T *, const T *, T *, int64_t, \
-                                              LayerShape, const GridP<T> &, hipStream_t);        \
-    template hipError_t launch_dx_generic<T>(ChanCfg, const T *, const T *, const T *, T *,      \
-                                             int64_t, LayerShape, const GridP<T> &, hipStream_t); \
-    template hipError_t launch_dw_generic<T>(ChanCfg, bool, const T *, const T *, T *, int,      \
-                                             int64_t, LayerShape, const GridP<T> &, hipStream_t); \
     template hipError_t launch_reduce_layers<T>(ReduceTable<T>, int, hipStream_t);                 \
     template hipError_t launch_adam<T>(AdamTable<T>, int64_t *, double, double, double, double, hipStream_t); \
     template hipError_t launch_residual<T>(const PdeParams &, int, const T *, const T *, int64_t, \

@@ -354,6 +354,8 @@ static int plan_create(hrkan_plan **out, const hrkan_net_desc *net, int32_t n_in
     for (int q = 0; q < n_inst; ++q) {
         rc = check_pde(&pdes[q]);
         if (rc != HRKAN_OK) return rc;
+        if (pdes[q].kind != HRKAN_BURGERS1D && pdes[q].kind != HRKAN_POISSON2D)
+            return fail(HRKAN_ERR_UNSUPPORTED, "instance %d: a plan takes Burgers or Poisson instances", q);
         if (pdes[q].kind != pdes[0].kind) return fail(HRKAN_ERR_INVALID_ARG, "instance %d: another PDE kind", q);
         const hrkan_points &p = pts[q];
         if ((p.n_int > 0 && !p.x_int) || (p.n_bc > 0 && (!p.x_bc || !p.g_bc)))
@@ -402,7 +404,7 @@ static int plan_build(hrkan_plan *p, const NetInfo &ni, int32_t n_inst, const hr
     p->ni = ni;
     p->n_inst = n_inst;
     p->kind = pdes[0].kind;
-    rc = mask_cfg(pde_mask(p->kind), &p->chi);
+    rc = mask_cfg(pde_mask(&pdes[0]), &p->chi);
     if (rc == HRKAN_OK) rc = mask_cfg(HRKAN_MASK_VALUE, &p->chb);
     p->pts.assign(pts, pts + n_inst);
     p->pdes.assign(pdes, pdes + n_inst);

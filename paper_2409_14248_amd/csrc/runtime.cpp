@@ -90,22 +90,56 @@ int check_net(const hrkan_net_desc *d, NetInfo *ni)
     }
     ni->n_params = 0;
     for (int l = 0; l < ni->L; ++l) ni->n_params += (int64_t)ni->w[l] * ni->nb * ni->w[l + 1];
+    ni->cw = 5;
+    ni->mc = true;
     return HRKAN_OK;
+}
+
+// The channel sets the matrix-core kernels take.
+static bool mc_channels(ChanCfg ch)
+{
+    return (ch.o0 == 0 && ch.o1 == 0) || (ch.o0 == 1 && ch.o1 == 1) ||
+           (ch.o0 == 2 && ch.o1 <= 2);
+}
+
+int apply_channels(NetInfo *ni, ChanCfg ch)
+{
+    ni->cw = std::max(5, ch.C());
+    ni->mc = mc_channels(ch);
+    if (!ni->mc && ni->dtype == HRKAN_BF16)
+        return fail(HRKAN_ERR_UNSUPPORTED,
+                    "HRKAN_BF16 runs the jet orders (%d, %d) on no kernel: the BF16 matrix-core kernels take "
+                    "at most second derivatives (U; U,X,Y; U,X,XX; U,X,XX,Y; U,X,XX,Y,YY)", ch.o0, ch.o1);
+    return HRKAN_OK;
+}
+
+// The derivative bits of each coordinate, by order 1..5.
+static const uint32_t XBITS[HRKAN_MAX_ORDER] = {HRKAN_CH_X, HRKAN_CH_XX, HRKAN_CH_X3, HRKAN_CH_X4, HRKAN_CH_X5};
+static const uint32_t YBITS[HRKAN_MAX_ORDER] = {HRKAN_CH_Y, HRKAN_CH_YY, HRKAN_CH_Y3, HRKAN_CH_Y4, HRKAN_CH_Y5};
+
+// Order of the derivatives of one coordinate in a mask: the bits of orders
+// 1..o and no other; -1 if there is a gap.
+static int axis_order(uint32_t mask, const uint32_t *bits)
+{
+    int o = 0;
+    while (o < HRKAN_MAX_ORDER && (mask & bits[o])) ++o;
+    for (int k = o; k < HRKAN_MAX_ORDER; ++k)
+        if (mask & bits[k]) return -1;
+    return o;
 }
 
 int mask_cfg(uint32_t mask, ChanCfg *ch)
 {
-    switch (mask) {
-    case HRKAN_CH_U: *ch = {0, 0}; return HRKAN_OK;
-    case HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_Y: *ch = {1, 1}; return HRKAN_OK;
-    case HRKAN_CH_U | HRKAN_CH_X | HRKAN_CH_XX: *ch = {2, 0}; return HRKAN_OK;
-    case HRKAN_MASK_BURGERS: *ch = {2, 1}; return HRKAN_OK;
-    case HRKAN_MASK_POISSON: *ch = {2, 2}; return HRKAN_OK;
-    default: break;
-    }
-    if (!(mask & HRKAN_CH_U) || mask > 31)
-        return fail(HRKAN_ERR_INVALID_ARG, "channel mask 0x%x: must contain U and only U,X,XX,Y,YY", mask);
-    return fail(HRKAN_ERR_UNSUPPORTED, "channel mask 0x%x is not a supported set", mask);
+    uint32_t all = HRKAN_CH_U;
+    for (int k = 0; k < HRKAN_MAX_ORDER; ++k) all |= XBITS[k] | YBITS[k];
+    if (!(mask & HRKAN_CH_U) || (mask & ~all))
+        return fail(HRKAN_ERR_INVALID_ARG, "channel mask 0x%x: must contain U and only the HRKAN_CH_* bits", mask);
+    const int ox = axis_order(mask, XBITS), oy = axis_order(mask, YBITS);
+    if (ox < 0 || oy < 0)
+        return fail(HRKAN_ERR_INVALID_ARG,
+                    "channel mask 0x%x: the derivatives of a coordinate must be those of order 1..o", mask);
+    *ch = {ox, oy};
+    return HRKAN_OK;
 }
 
 template <typename T>
@@ -139,7 +173,7 @@ int64_t saved_elems(const NetInfo &ni, int C, int64_t n)
 // layer shape allows it; FP64 (and other shapes) through the generic ones.
 bool use_bs32(const NetInfo &ni, int l)
 {
-    return ni.dtype != HRKAN_F64 && ni.m == 4 && ni.k == 3 &&
+    return ni.mc && ni.dtype != HRKAN_F64 && ni.m == 4 && ni.k == 3 &&
            bs32_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, l == 0);
 }
 
@@ -152,7 +186,7 @@ bool use_dn(const NetInfo &ni, int l)
         const char *e = getenv("HRKAN_BF16_DENSE");
         return !(e && e[0] == '0');
     }();
-    return enabled && ni.dtype == HRKAN_BF16 && ni.m == 4 && ni.k == 3 &&
+    return enabled && ni.mc && ni.dtype == HRKAN_BF16 && ni.m == 4 && ni.k == 3 &&
            dn_supported(LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, l == 0);
 }
 
@@ -170,7 +204,7 @@ bool tc_enabled()
 
 bool use_tc(const NetInfo &ni, int l)
 {
-    return tc_enabled() && ni.dtype == HRKAN_F32 &&
+    return tc_enabled() && ni.mc && ni.dtype == HRKAN_F32 &&
            tc_supported(ChanCfg{2, 2}, LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, ni.k, ni.m, l == 0);
 }
 
@@ -332,9 +366,10 @@ static int64_t part_elems_total(const NetInfo &ni, int64_t n_a, int64_t n_b)
     return m;
 }
 
-// Workspace regions, in bytes from the start of ws. Sizes use 5 channels for
-// interior sets so one layout serves both PDE kinds. A merged step keeps its
-// one set in the interior regions.
+// Workspace regions, in bytes from the start of ws. Sizes use ni.cw channels
+// (at least 5) for interior sets, so one layout serves the Poisson and
+// Burgers kinds and every call of either. A merged step keeps its one set in
+// the interior regions.
 WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
 {
     WsLayout L{};
@@ -348,14 +383,15 @@ WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
     L.nres = residual_blocks(n_int, n_bc);
     L.loss_part = take(sizeof(double) * 2 * (size_t)L.nres);
     L.xall = take(L.merged ? E * 2 * (size_t)na : 0);
-    L.sv_int = take(E * (size_t)saved_elems(ni, 5, na));
-    L.jets_int = take(E * 5 * (size_t)na);
+    const size_t cw = (size_t)ni.cw;
+    L.sv_int = take(E * (size_t)saved_elems(ni, ni.cw, na));
+    L.jets_int = take(E * cw * (size_t)na);
     L.sv_bc = take(E * (size_t)saved_elems(ni, 1, nbs));
     L.ubc = take(E * (size_t)nbs);
-    L.seed_int = take(E * 5 * (size_t)na);
+    L.seed_int = take(E * cw * (size_t)na);
     L.seed_bc = take(E * (size_t)nbs);
-    L.bars0 = take(E * 5 * (size_t)ni.maxw * nmax);
-    L.bars1 = take(E * 5 * (size_t)ni.maxw * nmax);
+    L.bars0 = take(E * cw * (size_t)ni.maxw * nmax);
+    L.bars1 = take(E * cw * (size_t)ni.maxw * nmax);
     L.bbars0 = take(E * (size_t)ni.maxw * nbs);
     L.bbars1 = take(E * (size_t)ni.maxw * nbs);
     L.part_elems = part_elems_total(ni, na, nbs);
@@ -373,14 +409,55 @@ WsLayout layout(const NetInfo &ni, int64_t n_int, int64_t n_bc)
 int check_pde(const hrkan_pde_desc *pde)
 {
     if (!pde) return fail(HRKAN_ERR_INVALID_ARG, "pde is NULL");
-    if (pde->kind != HRKAN_POISSON2D && pde->kind != HRKAN_BURGERS1D)
+    if (pde->kind != HRKAN_POISSON2D && pde->kind != HRKAN_BURGERS1D && pde->kind != HRKAN_LINEAR2D)
         return fail(HRKAN_ERR_INVALID_ARG, "pde kind %d unknown", pde->kind);
     if (!std::isfinite(pde->nu) || !std::isfinite(pde->alpha) || !std::isfinite(pde->adv))
         return fail(HRKAN_ERR_INVALID_ARG, "pde coefficients must be finite");
+    if (pde->kind == HRKAN_LINEAR2D) {
+        bool ok = std::isfinite(pde->c0);
+        for (int k = 0; k < HRKAN_MAX_ORDER; ++k) ok = ok && std::isfinite(pde->cx[k]) && std::isfinite(pde->cy[k]);
+        if (!ok) return fail(HRKAN_ERR_INVALID_ARG, "linear pde coefficients must be finite");
+    }
     return HRKAN_OK;
 }
 
-uint32_t pde_mask(int kind) { return kind == HRKAN_POISSON2D ? HRKAN_MASK_POISSON : HRKAN_MASK_BURGERS; }
+// Highest derivative order with a non-zero coefficient along x / y.
+static void linear_orders(const hrkan_pde_desc *pde, int *ox, int *oy)
+{
+    *ox = *oy = 0;
+    for (int k = 1; k <= HRKAN_MAX_ORDER; ++k) {
+        if (pde->cx[k - 1] != 0.0) *ox = k;
+        if (pde->cy[k - 1] != 0.0) *oy = k;
+    }
+}
+
+uint32_t pde_mask(const hrkan_pde_desc *pde)
+{
+    if (pde->kind == HRKAN_POISSON2D) return HRKAN_MASK_POISSON;
+    if (pde->kind == HRKAN_BURGERS1D) return HRKAN_MASK_BURGERS;
+    int ox, oy;
+    linear_orders(pde, &ox, &oy);
+    return hrkan_mask_of_orders(ox, oy);
+}
+
+PdeParams pde_params(const hrkan_pde_desc *pde)
+{
+    PdeParams p{};
+    p.kind = pde->kind;
+    p.nu = pde->nu;
+    p.alpha = pde->alpha;
+    p.adv = pde->adv;
+    if (pde->kind == HRKAN_LINEAR2D) {
+        p.c0 = pde->c0;
+        for (int k = 0; k < HRKAN_MAX_ORDER; ++k) {
+            p.cx[k] = pde->cx[k];
+            p.cy[k] = pde->cy[k];
+        }
+        linear_orders(pde, &p.ox, &p.oy);
+    }
+    return p;
+}
+
 
 }  // namespace hrk
 
@@ -611,7 +688,7 @@ int check_weights(const NetInfo &ni, const void *const *W, const char *what)
 
 extern "C" {
 
-int hrkan_version(void) { return 100; }
+int hrkan_version(void) { return 200; }
 
 const char *hrkan_status_string(int code)
 {
@@ -650,8 +727,9 @@ int hrkan_net_init(hrkan_net_desc *net)
 int hrkan_pde_init(hrkan_pde_desc *pde, int32_t kind)
 {
     if (!pde) return fail(HRKAN_ERR_INVALID_ARG, "pde is NULL");
-    if (kind != HRKAN_POISSON2D && kind != HRKAN_BURGERS1D)
+    if (kind != HRKAN_POISSON2D && kind != HRKAN_BURGERS1D && kind != HRKAN_LINEAR2D)
         return fail(HRKAN_ERR_INVALID_ARG, "pde kind %d unknown", kind);
+    std::memset(pde, 0, sizeof *pde);
     pde->kind = kind;
     pde->alpha = 0.05;
     pde->adv = 1.0;
@@ -664,6 +742,15 @@ int hrkan_mask_channels(uint32_t channel_mask)
     ChanCfg ch;
     TRY(mask_cfg(channel_mask, &ch));
     return ch.C();
+}
+
+uint32_t hrkan_mask_of_orders(int32_t ox, int32_t oy)
+{
+    if (ox < 0 || oy < 0 || ox > HRKAN_MAX_ORDER || oy > HRKAN_MAX_ORDER) return 0u;
+    uint32_t m = HRKAN_CH_U;
+    for (int k = 0; k < ox; ++k) m |= XBITS[k];
+    for (int k = 0; k < oy; ++k) m |= YBITS[k];
+    return m;
 }
 
 int hrkan_saved_bytes(const hrkan_net_desc *net, int64_t n, uint32_t channel_mask, size_t *bytes)
@@ -682,8 +769,11 @@ int hrkan_workspace_bytes(const hrkan_net_desc *net, const hrkan_pde_desc *pde, 
                           int64_t n_bc, size_t *bytes)
 {
     NetInfo ni;
+    ChanCfg chi;
     TRY(check_net(net, &ni));
     TRY(check_pde(pde));
+    TRY(mask_cfg(pde_mask(pde), &chi));
+    TRY(apply_channels(&ni, chi));
     if (n_int < 0 || n_bc < 0) return fail(HRKAN_ERR_INVALID_ARG, "negative point count");
     if (!bytes) return fail(HRKAN_ERR_INVALID_ARG, "bytes is NULL");
     *bytes = layout(ni, n_int, n_bc).total;
@@ -698,6 +788,7 @@ int hrkan_forward_jets(const hrkan_net_desc *net, const void *const *W, const vo
     ChanCfg ch;
     TRY(check_net(net, &ni));
     TRY(mask_cfg(channel_mask, &ch));
+    TRY(apply_channels(&ni, ch));
     if (n < 0) return fail(HRKAN_ERR_INVALID_ARG, "n < 0");
     TRY(check_weights(ni, W, "W"));
     if (n > 0 && (!x || !jets_out)) return fail(HRKAN_ERR_INVALID_ARG, "x or jets_out is NULL");
@@ -734,8 +825,8 @@ int hrkan_residual(const hrkan_pde_desc *pde, int32_t dtype, const void *jets_in
     TRY(check_ws(ws, ws_bytes, need));
     char *w = (char *)ws;
     double *partials = (double *)(w + 256);
-    const PdeParams pp{pde->kind, pde->nu, pde->alpha, pde->adv};
-    const int C = hrkan_mask_channels(pde_mask(pde->kind));
+    const PdeParams pp = pde_params(pde);
+    const int C = hrkan_mask_channels(pde_mask(pde));
     hipError_t e;
     if (dtype == HRKAN_F64)
         e = launch_residual<double>(pp, C, (const double *)jets_int, (const double *)pts->x_int,
@@ -762,6 +853,7 @@ int hrkan_backward(const hrkan_net_desc *net, const void *const *W, const void *
     ChanCfg ch;
     TRY(check_net(net, &ni));
     TRY(mask_cfg(channel_mask, &ch));
+    TRY(apply_channels(&ni, ch));
     if (n < 0) return fail(HRKAN_ERR_INVALID_ARG, "n < 0");
     TRY(check_weights(ni, W, "W"));
     TRY(check_weights(ni, (const void *const *)gW_out, "gW_out"));
@@ -799,8 +891,12 @@ int step_impl(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *
               size_t ws_bytes, hipStream_t stream, bool allow_fork)
 {
     NetInfo ni;
+    ChanCfg chi, chb;
     TRY(check_net(net, &ni));
     TRY(check_pde(pde));
+    TRY(mask_cfg(pde_mask(pde), &chi));
+    TRY(mask_cfg(HRKAN_MASK_VALUE, &chb));
+    TRY(apply_channels(&ni, chi));
     TRY(check_weights(ni, W, "W"));
     TRY(check_weights(ni, (const void *const *)gW_out, "gW_out"));
     if (!pts) return fail(HRKAN_ERR_INVALID_ARG, "pts is NULL");
@@ -815,11 +911,8 @@ int step_impl(const hrkan_net_desc *net, const hrkan_pde_desc *pde, const void *
     TRY(check_ws(ws, ws_bytes, need));
     const WsLayout L = layout(ni, pts->n_int, pts->n_bc);
     char *w = (char *)ws;
-    ChanCfg chi, chb;
-    TRY(mask_cfg(pde_mask(pde->kind), &chi));
-    TRY(mask_cfg(HRKAN_MASK_VALUE, &chb));
     const int64_t ni_ = pts->n_int, nb_ = pts->n_bc;
-    const PdeParams pp{pde->kind, pde->nu, pde->alpha, pde->adv};
+    const PdeParams pp = pde_params(pde);
 
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);

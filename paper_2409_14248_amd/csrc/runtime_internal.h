@@ -20,6 +20,12 @@ struct NetInfo {
     size_t elem;     // bytes of one array element (8 for F64, else 4)
     int maxw;
     int64_t n_params;
+    // channel sets of the call (apply_channels): interior jet channels the
+    // workspace regions are sized for (at least 5), and whether the layers
+    // may run on the matrix-core kernels (orders at most two, one of their
+    // channel sets)
+    int cw;
+    bool mc;
 };
 
 // Byte offsets of the workspace regions.
@@ -40,8 +46,10 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int check_net(const hrkan_net_desc *d, NetInfo *ni);
 int mask_cfg(uint32_t mask, ChanCfg *ch);
+int apply_channels(NetInfo *ni, ChanCfg ch);
 int check_pde(const hrkan_pde_desc *pde);
-uint32_t pde_mask(int kind);   // the interior channel mask of a PDE kind
+uint32_t pde_mask(const hrkan_pde_desc *pde);   // the interior channel mask of a PDE
+PdeParams pde_params(const hrkan_pde_desc *pde);
 template <typename T> GridP<T> make_grid(const NetInfo &ni);
 int64_t saved_elems(const NetInfo &ni, int C, int64_t n);
 int dw_splits(const NetInfo &ni, int l, int64_t n);

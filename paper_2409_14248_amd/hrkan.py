@@ -26,8 +26,10 @@ LIB_PATH = os.path.join(_PKG, "libhrkan.so")
 
 MAX_LAYERS = 8
 F64, F32, BF16 = 0, 1, 2
-POISSON2D, BURGERS1D = 0, 1
+POISSON2D, BURGERS1D, LINEAR2D = 0, 1, 2
+MAX_ORDER = 5
 CH_U, CH_X, CH_XX, CH_Y, CH_YY = 1, 2, 4, 8, 16
+CH_X3, CH_X4, CH_X5, CH_Y3, CH_Y4, CH_Y5 = 32, 64, 128, 256, 512, 1024
 MASK_POISSON = CH_U | CH_X | CH_XX | CH_Y | CH_YY
 MASK_BURGERS = CH_U | CH_X | CH_XX | CH_Y
 MASK_VALUE = CH_U
@@ -37,7 +39,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_PLAN_MISMAT
     0, -1, -2, -3, -4, -5, -6
 
 EXPORTS = [
-    "hrkan_net_init", "hrkan_pde_init", "hrkan_mask_channels", "hrkan_saved_bytes",
+    "hrkan_net_init", "hrkan_pde_init", "hrkan_mask_channels", "hrkan_mask_of_orders", "hrkan_saved_bytes",
     "hrkan_workspace_bytes", "hrkan_forward_jets", "hrkan_residual", "hrkan_backward",
     "hrkan_step", "hrkan_step_static", "hrkan_adam", "hrkan_plan_workspace_bytes", "hrkan_plan_create", "hrkan_plan_execute",
     "hrkan_plan_config", "hrkan_plan_destroy", "hrkan_read_status", "hrkan_status_string",
@@ -71,6 +73,9 @@ class PdeDesc(ctypes.Structure):
         ("nu", ctypes.c_double),
         ("alpha", ctypes.c_double),
         ("adv", ctypes.c_double),
+        ("c0", ctypes.c_double),
+        ("cx", ctypes.c_double * MAX_ORDER),
+        ("cy", ctypes.c_double * MAX_ORDER),
     ]
 
 
@@ -103,6 +108,7 @@ def lib():
     L.hrkan_net_init.argtypes = [P(NetDesc)]
     L.hrkan_pde_init.argtypes = [P(PdeDesc), i32]
     L.hrkan_mask_channels.argtypes = [u32]
+    L.hrkan_mask_of_orders.argtypes = [i32, i32]
     L.hrkan_saved_bytes.argtypes = [P(NetDesc), i64, u32, P(sz)]
     L.hrkan_workspace_bytes.argtypes = [P(NetDesc), P(PdeDesc), i64, i64, P(sz)]
     L.hrkan_forward_jets.argtypes = [P(NetDesc), P(vp), vp, i64, u32, vp, vp, vp, sz, vp]
@@ -124,6 +130,7 @@ def lib():
     L.hrkan_status_string.restype = ctypes.c_char_p
     L.hrkan_last_error.argtypes = []
     L.hrkan_last_error.restype = ctypes.c_char_p
+    L.hrkan_mask_of_orders.restype = u32
     L.hrkan_version.argtypes = []
     L.hrkan_profile_enable.argtypes = [i32]
     L.hrkan_profile_read.argtypes = [ctypes.c_char_p, sz]
@@ -160,11 +167,32 @@ def net_desc(net: _wl.Net, dtype="f32", bf16_split: int = 2) -> NetDesc:
 def pde_desc(pde: _wl.Pde) -> PdeDesc:
     p = PdeDesc()
     p.kind, p.nu, p.alpha, p.adv = int(pde.kind), float(pde.nu), float(pde.alpha), float(pde.adv)
+    p.c0 = float(getattr(pde, "c0", 0.0))
+    for k, v in enumerate(getattr(pde, "cx", ())):
+        p.cx[k] = float(v)
+    for k, v in enumerate(getattr(pde, "cy", ())):
+        p.cy[k] = float(v)
     return p
 
 
-def pde_mask(kind: int) -> int:
-    return MASK_POISSON if kind == POISSON2D else MASK_BURGERS
+def mask_of_orders(ox: int, oy: int) -> int:
+    """The mask of the value and the derivatives of order 1..ox along x and
+    1..oy along y."""
+    m = lib().hrkan_mask_of_orders(int(ox), int(oy))
+    if m == 0:
+        raise HrkanError(ERR_INVALID_ARG, f"orders ({ox}, {oy}) outside 0..{MAX_ORDER}")
+    return m
+
+
+def pde_mask(pde) -> int:
+    """Interior channel mask of a PDE (a workloads.Pde, or a kind for the
+    Poisson and Burgers kinds)."""
+    kind = pde if isinstance(pde, int) else int(pde.kind)
+    if kind == POISSON2D:
+        return MASK_POISSON
+    if kind == BURGERS1D:
+        return MASK_BURGERS
+    return mask_of_orders(*pde.orders)
 
 
 def mask_channels(mask: int) -> int:

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(H.EXPORTS)
-    assert L.hrkan_version() == 100
+    assert L.hrkan_version() == 200
 
 
 def test_status_strings():
@@ -54,15 +54,71 @@ def test_defaults():
 
 
 @pytest.mark.parametrize("mask,C", [(H.MASK_VALUE, 1), (H.MASK_BURGERS, 4), (H.MASK_POISSON, 5),
-                                    (H.CH_U | H.CH_X | H.CH_Y, 3), (H.CH_U | H.CH_X | H.CH_XX, 3)])
+                                    (H.CH_U | H.CH_X | H.CH_Y, 3), (H.CH_U | H.CH_X | H.CH_XX, 3),
+                                    (H.CH_U | H.CH_X, 2), (H.CH_U | H.CH_Y | H.CH_YY, 3),
+                                    (H.CH_U | H.CH_X | H.CH_XX | H.CH_X3 | H.CH_X4 | H.CH_Y, 6),
+                                    (H.CH_U | H.CH_X | H.CH_XX | H.CH_X3 | H.CH_X4 | H.CH_X5
+                                     | H.CH_Y | H.CH_YY | H.CH_Y3 | H.CH_Y4 | H.CH_Y5, 11)])
 def test_mask_channels(mask, C):
     assert H.mask_channels(mask) == C
 
 
-@pytest.mark.parametrize("mask,code", [(H.CH_X, H.ERR_INVALID_ARG), (64 | H.CH_U, H.ERR_INVALID_ARG),
-                                       (H.CH_U | H.CH_XX, H.ERR_UNSUPPORTED)])
+@pytest.mark.parametrize("mask,code", [(H.CH_X, H.ERR_INVALID_ARG), (H.CH_X4 | H.CH_U, H.ERR_INVALID_ARG),
+                                       (H.CH_U | H.CH_XX, H.ERR_INVALID_ARG),
+                                       (H.CH_U | H.CH_Y | H.CH_Y3, H.ERR_INVALID_ARG),
+                                       (H.CH_U | (1 << 11), H.ERR_INVALID_ARG)])
 def test_bad_masks(mask, code):
+    """U is required, the derivatives of a coordinate must be those of
+    order 1..o, and only the defined bits may be set."""
     assert H.lib().hrkan_mask_channels(mask) == code
+
+
+@pytest.mark.parametrize("ox,oy", [(0, 0), (2, 2), (2, 1), (4, 4), (5, 1), (0, 3), (5, 5)])
+def test_mask_of_orders(ox, oy):
+    m = H.mask_of_orders(ox, oy)
+    assert H.mask_channels(m) == 1 + ox + oy
+    assert H.lib().hrkan_mask_of_orders(6, 0) == 0
+    assert H.lib().hrkan_mask_of_orders(0, -1) == 0
+    if (ox, oy) == (2, 2):
+        assert m == H.MASK_POISSON
+    if (ox, oy) == (2, 1):
+        assert m == H.MASK_BURGERS
+
+
+def test_linear_pde_masks_and_bf16_refusal():
+    """The linear kind's mask follows its highest non-zero coefficients; the
+    BF16 kernels take at most second derivatives, so a BF16 network with a
+    fourth-order PDE is refused, while FP32 and FP64 are accepted."""
+    pde = WL.Pde(WL.LINEAR2D, cx=(0, 0, 0, 1), cy=(0, 0, 0, 1))
+    assert H.pde_mask(pde) == H.mask_of_orders(4, 4)
+    assert H.pde_mask(WL.Pde(WL.LINEAR2D, c0=1.0, cx=(1,), cy=(0, 0, 0, 0, 2))) == H.mask_of_orders(1, 5)
+    pd = H.pde_desc(pde)
+    b = ctypes.c_size_t(0)
+    for dt, code in [(H.F64, H.OK), (H.F32, H.OK), (H.BF16, H.ERR_UNSUPPORTED)]:
+        nd = nd_of((2, 32, 32, 1), G=10)
+        nd.dtype, nd.bf16_split = dt, 2
+        assert H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(pd), 100, 16, ctypes.byref(b)) == code
+    # a linear PDE with second derivatives runs on BF16 like Poisson
+    nd = nd_of((2, 32, 32, 1), G=10)
+    nd.dtype, nd.bf16_split = H.BF16, 2
+    pd2 = H.pde_desc(WL.Pde(WL.LINEAR2D, cx=(0, 1), cy=(0, 1)))
+    assert H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(pd2), 100, 16, ctypes.byref(b)) == H.OK
+    # non-finite coefficients are refused
+    pd.cx[2] = float("inf")
+    assert H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(pd), 100, 16, ctypes.byref(b)) == \
+        H.ERR_INVALID_ARG
+
+
+def test_workspace_grows_with_jet_order():
+    """Interior regions are sized for max(5, C) channels."""
+    nd = nd_of((2, 32, 32, 1), G=10)
+    nd.dtype = H.F64
+    b2, b5 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    p2 = H.pde_desc(WL.Pde(WL.POISSON2D))
+    p5 = H.pde_desc(WL.Pde(WL.LINEAR2D, cx=(0, 0, 0, 0, 1), cy=(0, 0, 0, 0, 1)))
+    assert H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(p2), 4096, 256, ctypes.byref(b2)) == H.OK
+    assert H.lib().hrkan_workspace_bytes(ctypes.byref(nd), ctypes.byref(p5), 4096, 256, ctypes.byref(b5)) == H.OK
+    assert b5.value > b2.value
 
 
 @pytest.mark.parametrize("mutate,code", [
@@ -152,8 +208,11 @@ def test_forward_argument_errors():
     ws_off = FakeDev(need, offset=64)
     assert _fwd(nd, W, x.p, 64, H.MASK_POISSON, out.p, None, ws_off.p, need) == H.ERR_INVALID_ARG
     assert _fwd(nd, W, x.p, 64, H.MASK_POISSON, out.p, None, ws.p, 100) == H.ERR_WORKSPACE
-    # unsupported mask
-    assert _fwd(nd, W, x.p, 64, H.CH_U | H.CH_YY, out.p, None, ws.p, need) == H.ERR_UNSUPPORTED
+    # a mask with a gap in its derivative orders
+    assert _fwd(nd, W, x.p, 64, H.CH_U | H.CH_YY, out.p, None, ws.p, need) == H.ERR_INVALID_ARG
+    # a mask of more channels than the workspace was sized for (Poisson: 5)
+    m44 = H.mask_of_orders(4, 4)
+    assert _fwd(nd, W, x.p, 64, m44, out.p, None, ws.p, need) == H.ERR_WORKSPACE
     # n = 0 is a valid empty call that enqueues nothing
     assert _fwd(nd, W, x.p, 0, H.MASK_POISSON, out.p, None, ws.p, need) == H.OK
 

@@ -82,7 +82,7 @@ def test_full_size_jets_and_residual_f32(name):
     max-scaled element-wise."""
     pr = _problem(name)
     q = pr.rounded(np.float32)
-    mask = H.pde_mask(pr.pde.kind)
+    mask = H.pde_mask(pr.pde)
     nd = H.net_desc(pr.net, "f32")
     pd = H.pde_desc(pr.pde)
     W = [to_dev(w, "f32") for w in pr.W]

@@ -41,7 +41,7 @@ def sample_points(n, seed):
 def test_full_size_forward_jets_at_sampled_points(name, dtype):
     pr = WL.make_problem(WL.WORKLOADS[name])
     q = pr.rounded(np.float32)
-    mask = H.pde_mask(pr.pde.kind)
+    mask = H.pde_mask(pr.pde)
     nd = H.net_desc(pr.net, dtype, 2)
     pd = H.pde_desc(pr.pde)
     W = [to_dev(w, "f32") for w in pr.W]
