@@ -202,10 +202,22 @@ bool tc_enabled()
     return enabled;
 }
 
-bool use_tc(const NetInfo &ni, int l)
+// Where the tile-coherent kernels beat the block-sparse ones, measured per
+// stage on the FP32 steps (ms per launch, sets ordered along the curve):
+//  - 32-output layers (c2): never: the point ordering alone (0.12 ms for
+//    65,536 + 4,096 points) costs more than they save;
+//  - 64 outputs (c3): forward (0.61 against 1.33) and weight gradient (1.52
+//    against 1.89), not the input bars (1.95 against 1.59);
+//  - 128 outputs (c4): every stage (forward 7.0 against 18.2, input bars
+//    13.3 against 20.9, weight gradient 19.2 against 24.3).
+// stage: 'f' forward, 'x' input bars, 'w' weight gradient.
+bool use_tc(const NetInfo &ni, int l, char stage)
 {
-    return tc_enabled() && ni.mc && ni.dtype == HRKAN_F32 &&
-           tc_supported(ChanCfg{2, 2}, LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, ni.k, ni.m, l == 0);
+    if (!(tc_enabled() && ni.mc && ni.dtype == HRKAN_F32 &&
+          tc_supported(ChanCfg{2, 2}, LayerShape{ni.w[l], ni.w[l + 1], ni.nb}, ni.k, ni.m, l == 0)))
+        return false;
+    const int N = ni.w[l + 1];
+    return stage == 'x' ? N >= 128 : N >= 64;
 }
 
 // A training step orders each point set along a Z-order curve first (in the
@@ -215,7 +227,7 @@ bool sorted_sets(const NetInfo &ni, int64_t n_int, int64_t n_bc)
 {
     if (merged_sets(ni, n_int, n_bc) || n_int > ((int64_t)1 << 24) || n_bc > ((int64_t)1 << 24)) return false;
     for (int l = 0; l < ni.L; ++l)
-        if (use_tc(ni, l)) return true;
+        if (use_tc(ni, l, 'f') || use_tc(ni, l, 'x') || use_tc(ni, l, 'w')) return true;
     return false;
 }
 
@@ -248,7 +260,7 @@ int dw_splits(const NetInfo &ni, int l, int64_t n)
     if (n <= 0) return 0;
     const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
     if (use_dn(ni, l)) return dw_dn_splits(n, ls);
-    if (use_tc(ni, l)) return dw_tc_splits(n, ls);
+    if (use_tc(ni, l, 'w')) return dw_tc_splits(n, ls);
     return use_bs32(ni, l) ? dw_bs32_splits(n, ls) : dw_generic_splits(n, ls);
 }
 
@@ -493,7 +505,7 @@ int forward_impl(const NetInfo &ni, ChanCfg ch, const T *const *W, const T *x, i
             if constexpr (std::is_same<T, float>::value) {
                 if (use_dn(ni, l))
                     e = launch_fwd_dn(ch, zin, wdn + wdn_offset(ni, l), zout, n, ls, g, ni.S, st);
-                else if (use_tc(ni, l))
+                else if (use_tc(ni, l, 'f'))
                     e = launch_fwd_tc(ch, l == 0, zin, W[l], zout, n, ls, make_tc_grid(ni.lo, ni.hi, ni.G, ni.k),
                                       cu_blocks(), st);
                 else if (use_bs32(ni, l))
@@ -560,7 +572,7 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             if constexpr (std::is_same<T, float>::value) {
                 if (use_dn(ni, l))
                     e = launch_dw_dn(S.ch, zin, ybar, dst, ns, S.n, ls, g, ni.S, st);
-                else if (use_tc(ni, l))
+                else if (use_tc(ni, l, 'w'))
                     e = launch_dw_tc(S.ch, l == 0, zin, ybar, dst, ns, S.n, ls, make_tc_grid(ni.lo, ni.hi, ni.G, ni.k),
                                      st);
                 else if (use_bs32(ni, l))
@@ -579,7 +591,7 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
             if constexpr (std::is_same<T, float>::value) {
                 if (use_dn(ni, l))
                     e = launch_dx_dn(S.ch, zin, ybar, wdn + wdn_offset(ni, l), zbar, S.n, ls, g, ni.S, st);
-                else if (use_tc(ni, l))
+                else if (use_tc(ni, l, 'x'))
                     e = launch_dx_tc(S.ch, zin, ybar, W[l], zbar, S.n, ls, make_tc_grid(ni.lo, ni.hi, ni.G, ni.k),
                                      cu_blocks(), st);
                 else if (use_bs32(ni, l))
