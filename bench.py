@@ -181,7 +181,7 @@ def cpu_baseline_leg(pr, dtype, args, want_bf16_weights):
         master = O.step(q.net, q.pde, q.W, q.x_int, q.x_bc, q.g_bc)
         reps += 1
         el = time.time() - t
-        if el >= args.cpu_seconds or reps >= 30:
+        if el >= args.cpu_seconds or reps >= 200:
             break
     cpu = {"value": round(reps * q.n_int / el, 1), "unit": "points/s", "cores": O.num_threads(),
            "kind": "oracle", "cpu_model": cpu_model(),
