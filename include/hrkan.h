@@ -283,7 +283,15 @@ typedef struct hrkan_plan hrkan_plan;
 
 /* Create a plan (host call; may allocate host memory and run the tile
  * autotuner, which times candidate tile shapes on `stream` with the caller's
- * buffers; it never allocates device memory).
+ * buffers; it never allocates device memory). The autotuner's choice is
+ * kept in a cache file keyed by the device architecture, the network shape,
+ * dtype, PDE kind and the instance and interior point counts rounded up to
+ * powers of two; a later plan with the same key reads it instead of timing
+ * the candidates. The file is $HRKAN_AUTOTUNE_CACHE (an empty value turns
+ * the cache off), else $XDG_CACHE_HOME/hrkan/autotune.json, else
+ * $HOME/.cache/hrkan/autotune.json; it is written atomically (temporary
+ * file and rename), and a missing, unreadable or unwritable file only costs
+ * the timing.
  *   n_inst     number of instances (>= 1)
  *   pdes       host array [n_inst] (kind must be HRKAN_BURGERS1D or
  *              HRKAN_POISSON2D, one kind for all instances)
@@ -307,6 +315,10 @@ int hrkan_plan_execute(hrkan_plan *plan, hipStream_t stream);
 /* Tile configuration the autotuner chose (host ints: points per tile, work
  * items per persistent block); either pointer may be NULL. */
 int hrkan_plan_config(const hrkan_plan *plan, int32_t *tile_points, int32_t *blocks);
+/* Whether the plan's configuration came from the autotune cache (host int,
+ * 1 or 0) and the step time (ms, host double) measured for it when it was
+ * tuned; either pointer may be NULL. */
+int hrkan_plan_autotune_info(const hrkan_plan *plan, int32_t *from_cache, double *step_ms);
 void hrkan_plan_destroy(hrkan_plan *plan);
 
 /* Read and clear the device status word kept in ws (synchronises stream).

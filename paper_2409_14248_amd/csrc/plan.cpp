@@ -14,6 +14,7 @@
 #include <new>
 #include <vector>
 
+#include "autotune.h"
 #include "batch.h"
 #include "kernels_bs.h"
 #include "runtime_internal.h"
@@ -136,6 +137,8 @@ struct hrkan_plan {
     int nsl_int, nsl_bc;
     int64_t woff[HRKAN_MAX_LAYERS];
     int dev;
+    bool from_cache;     // the configuration came from the autotune cache
+    double tune_ms;      // its measured step time (ms)
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -421,25 +424,47 @@ static int plan_build(hrkan_plan *p, const NetInfo &ni, int32_t n_inst, const hr
     }
     if (rc == HRKAN_OK && hipGetDevice(&p->dev) != hipSuccess) rc = fail(HRKAN_ERR_DEVICE, "hipGetDevice");
 
-    // autotune: every candidate timed on the caller's buffers
+    // autotune: the cached choice for this kind of batch (device
+    // architecture, network, dtype, PDE kind, instance and point counts in
+    // powers of two), else every candidate timed on the caller's buffers and
+    // the winner stored in the cache
     PlanCfg best{SLICES[0], 0, cu_blocks()};
     float best_ms = INFINITY;
-    for (int P : SLICES) {
-        if (rc != HRKAN_OK) break;
-        rc = upload_tables(p, P);
-        for (int ii : DW_II) {
+    char arch[256] = "";
+    hipDeviceProp_t prop;
+    if (rc == HRKAN_OK && hipGetDeviceProperties(&prop, p->dev) == hipSuccess)
+        snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    int64_t total = 0;
+    for (int q = 0; q < n_inst; ++q) total += pts[q].n_int;
+    const std::string path = tune_cache_path();
+    const std::string key = tune_key(arch, ni, p->kind, n_inst, total);
+    TunedCfg tc{};
+    p->from_cache = rc == HRKAN_OK && tune_lookup(path, key, &tc) &&
+                    std::find(std::begin(SLICES), std::end(SLICES), tc.slice_pts) != std::end(SLICES) &&
+                    std::find(std::begin(DW_II), std::end(DW_II), tc.dw_ii) != std::end(DW_II);
+    if (p->from_cache) {
+        best = PlanCfg{tc.slice_pts, tc.dw_ii, cu_blocks()};
+        best_ms = (float)tc.ms;
+    } else {
+        for (int P : SLICES) {
             if (rc != HRKAN_OK) break;
-            const PlanCfg c{P, ii, cu_blocks()};
-            float ms = 0.f;
-            rc = time_cfg(p, c, stream, 2, &ms);
-            if (rc == HRKAN_OK && ms < best_ms) {
-                best_ms = ms;
-                best = c;
+            rc = upload_tables(p, P);
+            for (int ii : DW_II) {
+                if (rc != HRKAN_OK) break;
+                const PlanCfg c{P, ii, cu_blocks()};
+                float ms = 0.f;
+                rc = time_cfg(p, c, stream, 2, &ms);
+                if (rc == HRKAN_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
             }
         }
+        if (rc == HRKAN_OK) tune_store(path, key, TunedCfg{best.slice_pts, best.dw_ii, (double)best_ms});
     }
     if (rc == HRKAN_OK) rc = upload_tables(p, best.slice_pts);
     p->cfg = best;
+    p->tune_ms = best_ms;
     // capture one step into a graph, on a private stream (the caller's may be
     // the null stream, which cannot be captured); nothing runs during capture
     if (rc == HRKAN_OK) {
@@ -494,6 +519,14 @@ int hrkan_plan_config(const hrkan_plan *plan, int32_t *tile_points, int32_t *blo
     if (!plan) return fail(HRKAN_ERR_PLAN_MISMATCH, "plan is NULL");
     if (tile_points) *tile_points = plan->cfg.slice_pts;
     if (blocks) *blocks = plan->cfg.blocks;
+    return HRKAN_OK;
+}
+
+int hrkan_plan_autotune_info(const hrkan_plan *plan, int32_t *from_cache, double *step_ms)
+{
+    if (!plan) return fail(HRKAN_ERR_PLAN_MISMATCH, "plan is NULL");
+    if (from_cache) *from_cache = plan->from_cache ? 1 : 0;
+    if (step_ms) *step_ms = plan->tune_ms;
     return HRKAN_OK;
 }
 

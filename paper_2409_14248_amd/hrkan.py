@@ -42,7 +42,7 @@ EXPORTS = [
     "hrkan_net_init", "hrkan_pde_init", "hrkan_mask_channels", "hrkan_mask_of_orders", "hrkan_saved_bytes",
     "hrkan_workspace_bytes", "hrkan_forward_jets", "hrkan_residual", "hrkan_backward",
     "hrkan_step", "hrkan_step_static", "hrkan_adam", "hrkan_plan_workspace_bytes", "hrkan_plan_create", "hrkan_plan_execute",
-    "hrkan_plan_config", "hrkan_plan_destroy", "hrkan_read_status", "hrkan_status_string",
+    "hrkan_plan_config", "hrkan_plan_autotune_info", "hrkan_plan_destroy", "hrkan_read_status", "hrkan_status_string",
     "hrkan_last_error", "hrkan_version", "hrkan_profile_enable", "hrkan_profile_read",
 ]
 
@@ -123,6 +123,7 @@ def lib():
                                     sz, vp]
     L.hrkan_plan_execute.argtypes = [vp, vp]
     L.hrkan_plan_config.argtypes = [vp, P(i32), P(i32)]
+    L.hrkan_plan_autotune_info.argtypes = [vp, P(i32), P(ctypes.c_double)]
     L.hrkan_plan_destroy.argtypes = [vp]
     L.hrkan_plan_destroy.restype = None
     L.hrkan_read_status.argtypes = [vp, sz, vp, P(u32)]
@@ -560,6 +561,12 @@ class Plan:
         tp, bl = ctypes.c_int32(0), ctypes.c_int32(0)
         check(lib().hrkan_plan_config(self._h, ctypes.byref(tp), ctypes.byref(bl)))
         return tp.value, bl.value
+
+    def autotune_info(self):
+        """(configuration read from the autotune cache, its step time in ms)."""
+        fc, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+        check(lib().hrkan_plan_autotune_info(self._h, ctypes.byref(fc), ctypes.byref(ms)))
+        return bool(fc.value), ms.value
 
     def layer_grads(self, q: int, net: _wl.Net) -> List[torch.Tensor]:
         """Instance q's gradient, split into the per-layer [w_l * n_b, w_{l+1}] arrays."""

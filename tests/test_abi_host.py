@@ -292,6 +292,7 @@ def test_plan_calls_reject_null_plan():
     L = H.lib()
     assert L.hrkan_plan_execute(None, None) == H.ERR_PLAN_MISMATCH
     assert L.hrkan_plan_config(None, None, None) == H.ERR_PLAN_MISMATCH
+    assert L.hrkan_plan_autotune_info(None, None, None) == H.ERR_PLAN_MISMATCH
     L.hrkan_plan_destroy(None)
 
 

@@ -114,3 +114,41 @@ def test_batched_replays_are_identical_and_follow_weight_updates():
             o += r * c
         new.append(WL.Problem(pr.net, pr.pde, Ws, pr.x_int, pr.x_bc, pr.g_bc))
     _check_against_single_steps(plan, new)
+
+
+def test_autotune_cache_is_written_and_reused(tmp_path, monkeypatch):
+    """The first plan of a kind of batch times the candidates and stores the
+    winner under its key; a second plan of the same kind reads it (no
+    timing) and gives the same step bit for bit; a batch in another point
+    bucket is tuned anew."""
+    import json
+    cache = tmp_path / "autotune.json"
+    monkeypatch.setenv("HRKAN_AUTOTUNE_CACHE", str(cache))
+    probs = _instances(5)
+    p1 = H.Plan(probs)
+    c1, ms1 = p1.autotune_info()
+    assert not c1 and ms1 > 0
+    doc = json.loads(cache.read_text())
+    assert doc["hrkan_autotune"] == 1 and len(doc["entries"]) == 1
+    key = next(iter(doc["entries"]))
+    print(f"[autotune] key {key}: {doc['entries'][key]}", flush=True)
+    assert "|w=2,32,32,1|G=10|k=3|m=4|" in key and "|inst=2^3|" in key
+    assert doc["entries"][key]["slice_pts"] == p1.config()[0]
+    p2 = H.Plan(probs)
+    c2, ms2 = p2.autotune_info()
+    assert c2 and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert p2.config() == p1.config()
+    p1.execute()
+    p2.execute()
+    torch.cuda.synchronize()
+    assert torch.equal(p1.loss, p2.loss) and torch.equal(p1.gW, p2.gW)
+    p3 = H.Plan(_instances(5, lo=20000, hi=30000))
+    assert not p3.autotune_info()[0]
+    assert len(json.loads(cache.read_text())["entries"]) == 2
+    for p in (p1, p2, p3):
+        p.close()
+    # an empty value turns the cache off
+    monkeypatch.setenv("HRKAN_AUTOTUNE_CACHE", "")
+    p4 = H.Plan(probs)
+    assert not p4.autotune_info()[0]
+    p4.close()
