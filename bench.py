@@ -352,8 +352,9 @@ def main():
 
 
 def bench_batched(args, wl):
-    """Batched instances: one plan (one HIP graph launch per step) against the
-    plain FP32 step called once per instance."""
+    """Batched instances: one plan (one HIP graph launch per step, FP32 or
+    BF16 with --dtype bf16) against the plain step of the same dtype called
+    once per instance."""
     import numpy as np
     import torch
 
@@ -363,8 +364,11 @@ def bench_batched(args, wl):
     probs = WL.batched_instances(wl)
     n_int = sum(p.n_int for p in probs)
     n_bc = sum(p.n_bc for p in probs)
+    dtype = args.dtype or "f32"
+    if dtype == "f64":
+        raise SystemExit("batched plans run f32 or bf16")
     t0 = time.time()
-    plan = H.Plan(probs)
+    plan = H.Plan(probs, dtype=dtype, bf16_split=args.bf16_split)
     torch.cuda.synchronize()
     create_s = time.time() - t0
 
@@ -383,8 +387,8 @@ def bench_batched(args, wl):
         plan.execute()
     ms = timed(plan.execute, args.steps)
 
-    # the plain FP32 step, once per instance (eager launches, shared workspace)
-    nd = H.net_desc(probs[0].net, "f32")
+    # the plain step, once per instance (eager launches, shared workspace)
+    nd = H.net_desc(probs[0].net, dtype, args.bf16_split)
     ws = H.alloc_workspace(max(H.workspace_bytes(nd, H.pde_desc(p.pde), p.n_int, p.n_bc) for p in probs))
     dev = [([torch.as_tensor(w, dtype=torch.float32, device="cuda") for w in p.W],
             torch.as_tensor(p.x_int, dtype=torch.float32, device="cuda"),
@@ -400,10 +404,16 @@ def bench_batched(args, wl):
     looped()
     loop_ms = timed(looped, max(1, args.steps // 10))
 
-    f_pt = sum(v for v in layer_flops(probs[0].net, 4, 1).values())
-    f_bc = sum(v for v in layer_flops(probs[0].net, 1, 1).values())
+    # executed flops: the k+1 live basis rows per input (the dense-equivalent
+    # count of every basis row is an extra key, not a roofline fraction)
+    f_pt = sum(v for v in layer_flops(probs[0].net, 4, 1, live=True).values())
+    f_bc = sum(v for v in layer_flops(probs[0].net, 1, 1, live=True).values())
     step_flops = f_pt * n_int + f_bc * n_bc
     achieved = step_flops / (ms * 1e-3) / 1e12
+    d_pt = sum(v for v in layer_flops(probs[0].net, 4, 1).values())
+    d_bc = sum(v for v in layer_flops(probs[0].net, 1, 1).values())
+    dense = (d_pt * n_int + d_bc * n_bc) / (ms * 1e-3) / 1e12
+    peak = PEAK["bf16" if dtype == "bf16" else "f32"]
     tp, blocks = plan.config()
     out = {
         "metric": METRIC,
@@ -412,7 +422,7 @@ def bench_batched(args, wl):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": dtype, "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(probs), "widths": list(probs[0].net.widths),
                    "G": probs[0].net.G, "n_int_total": n_int, "n_bc_total": n_bc,
                    "tile_points": tp, "blocks": blocks},
@@ -422,8 +432,8 @@ def bench_batched(args, wl):
         "looped_points_per_s": round(n_int / (loop_ms * 1e-3), 1),
         "speedup_vs_looped": round(loop_ms / ms, 3),
         "roofline": {"bound": "mfma", "kernel": "whole batched step (one graph)", "achieved": round(achieved, 3),
-                     "peak": PEAK["f32"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["f32"], 4),
-                     "traffic": None},
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": None, "achieved_dense_equivalent": round(dense, 3)},
         "cpu_baseline": None,
     }
     print(json.dumps(out))

@@ -301,8 +301,9 @@ typedef struct hrkan_plan hrkan_plan;
  *   loss_out   device double [n_inst][3]
  *   gW_packed  [n_inst][n_params] gradients (overwritten at each execute)
  *   ws         workspace of hrkan_plan_workspace_bytes(...) bytes
- * The plan keeps every pointer until hrkan_plan_destroy. Only HRKAN_F32 is
- * supported. */
+ * The plan keeps every pointer until hrkan_plan_destroy. HRKAN_F32 and
+ * HRKAN_BF16 (the block-sparse matrix-core kernels with bf16_split product
+ * terms; FP32 master weights) are supported, HRKAN_F64 is refused. */
 int hrkan_plan_workspace_bytes(const hrkan_net_desc *net, int32_t n_inst,
                                const hrkan_points *pts /* host [n_inst] */,
                                size_t *bytes /* host */);

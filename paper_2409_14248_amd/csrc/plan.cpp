@@ -94,7 +94,7 @@ int check_plan_net(const hrkan_net_desc *net, NetInfo *ni)
 {
     int rc = check_net(net, ni);
     if (rc != HRKAN_OK) return rc;
-    if (ni->dtype != HRKAN_F32) return fail(HRKAN_ERR_UNSUPPORTED, "batched plans run HRKAN_F32 only");
+    if (ni->dtype == HRKAN_F64) return fail(HRKAN_ERR_UNSUPPORTED, "batched plans run HRKAN_F32 or HRKAN_BF16");
     for (int l = 0; l < ni->L; ++l)
         if (!use_bs32(*ni, l))
             return fail(HRKAN_ERR_UNSUPPORTED, "batched plans need k = 3, m = 4 and matrix-core layer shapes");
@@ -242,7 +242,8 @@ int enqueue(const hrkan_plan *p, const PlanCfg &cfg, hipStream_t st)
             float *zout = (l == ni.L - 1) ? out : saved + soff;
             if (l < ni.L - 1) soff += (int64_t)ch.C() * ni.w[l + 1] * n;
             const LayerShape ls{ni.w[l], ni.w[l + 1], ni.nb};
-            PTRY(launch_fwd_bs32(ch, l == 0, zin, p->W + p->woff[l], zout, n, ls, g, cfg.blocks, 0, st, bm));
+            PTRY(launch_fwd_bs32(ch, l == 0, zin, p->W + p->woff[l], zout, n, ls, g, cfg.blocks, bf16_terms(ni), st,
+                                 bm));
             zin = zout;
         }
         return HRKAN_OK;
@@ -272,11 +273,11 @@ int enqueue(const hrkan_plan *p, const PlanCfg &cfg, hipStream_t st)
             int64_t off = 0;
             for (int q = 1; q < l; ++q) off += (int64_t)ch.C() * ni.w[q] * n;
             const float *zin = l == 0 ? x : saved + off;
-            PTRY(launch_dw_bs32(ch, l == 0, zin, ybar, part + base[l] + (int64_t)slot0 * kn[l], nsl, n, ls, g, 0,
+            PTRY(launch_dw_bs32(ch, l == 0, zin, ybar, part + base[l] + (int64_t)slot0 * kn[l], nsl, n, ls, g, bf16_terms(ni),
                                 st, bm, cfg.dw_ii));
             if (l == 0) break;
             float *zbar = (ybar == bar0) ? bar1 : bar0;
-            PTRY(launch_dx_bs32(ch, zin, ybar, p->W + p->woff[l], zbar, n, ls, g, cfg.blocks, 0, st, bm));
+            PTRY(launch_dx_bs32(ch, zin, ybar, p->W + p->woff[l], zbar, n, ls, g, cfg.blocks, bf16_terms(ni), st, bm));
             ybar = zbar;
         }
         return HRKAN_OK;

@@ -531,9 +531,10 @@ class Plan:
     steps), and the outputs loss [n_inst, 3] (float64) and gW [n_inst,
     n_params]. execute() is one HIP graph launch."""
 
-    def __init__(self, problems: Sequence[_wl.Problem], device="cuda", stream=None):
+    def __init__(self, problems: Sequence[_wl.Problem], device="cuda", stream=None, dtype="f32",
+                 bf16_split: int = 2):
         net = problems[0].net
-        self.nd = net_desc(net, "f32")
+        self.nd = net_desc(net, dtype, bf16_split)
         self.n_inst = len(problems)
         to = lambda a, shape=None: torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
         self.x_int = [to(p.x_int) for p in problems]

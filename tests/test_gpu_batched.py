@@ -152,3 +152,26 @@ def test_autotune_cache_is_written_and_reused(tmp_path, monkeypatch):
     p4 = H.Plan(probs)
     assert not p4.autotune_info()[0]
     p4.close()
+
+
+@pytest.mark.parametrize("S", [2, 3])
+def test_bf16_batched_plan_against_oracle(S):
+    """BF16 plans (block-sparse kernels, S product terms, FP32 master
+    weights) against the FP64 oracle at the literal 2e-2: on the master
+    weights for S = 3, on the BF16-rounded weights for S = 2 (only their high
+    piece enters the products)."""
+    from gpu_util import bf16_round
+    probs = _instances(4, lo=2000, hi=6000)
+    plan = H.Plan(probs, dtype="bf16", bf16_split=S)
+    plan.execute()
+    torch.cuda.synchronize()
+    assert H.read_status(plan.ws) == 0
+    loss = plan.loss.cpu().numpy()
+    for q in (0, 3):
+        qq = probs[q].rounded(np.float32)
+        W = qq.W if S == 3 else [bf16_round(w) for w in qq.W]
+        ref = O.step(qq.net, qq.pde, W, qq.x_int, qq.x_bc, qq.g_bc)
+        check(f"bf16 plan S{S} instance {q} loss", relerr(loss[q], ref["loss"]), 2e-2)
+        for l, g in enumerate(plan.layer_grads(q, probs[q].net)):
+            check(f"bf16 plan S{S} instance {q} gW{l}", relerr(g.double().cpu().numpy(), ref["gW"][l]), 2e-2)
+    plan.close()
