@@ -490,20 +490,31 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
                     }
                     __builtin_amdgcn_wave_barrier();
                     // per (channel, point): the block's entries in order, one
-                    // running sum per input
+                    // running sum per input. The entries' inputs are the same
+                    // for every lane: taken once into scalar registers, so the
+                    // branches are uniform and the 16 term reads independent.
                     const int ne = min(16, tot - eb * 16);
+                    const int my_in = L.ent[min(eb * 16 + r16, tot - 1)] >> 8;
+                    int ein[16];
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) ein[e] = __builtin_amdgcn_readlane(my_in, e);
                     for (int cp = lane; cp < C * TPT; cp += 64) {
                         const int c = cp / TPT, p = cp % TPT;
-                        int cur = L.ent[eb * 16] >> 8;
+                        float tv[16];
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) tv[e] = L.tm[e][c][p];
+                        int cur = ein[0];
                         float run = 0.f;
-                        for (int e = 0; e < ne; ++e) {
-                            const int il = L.ent[eb * 16 + e] >> 8;
-                            if (il != cur) {
-                                L.zb[c][cur][p] += run;
-                                run = 0.f;
-                                cur = il;
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) {
+                            if (e < ne) {
+                                if (ein[e] != cur) {
+                                    L.zb[c][cur][p] += run;
+                                    run = 0.f;
+                                    cur = ein[e];
+                                }
+                                run += tv[e];
                             }
-                            run += L.tm[e][c][p];
                         }
                         L.zb[c][cur][p] += run;
                     }
