@@ -560,7 +560,7 @@ struct TcDwLds {
     unsigned short ent[TDI * MAXNB];
 };
 
-template <int O0, int O1, bool FIRST, int NT16>
+template <int O0, int O1, bool FIRST, int NT16, bool VEC>
 __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin, const float *__restrict__ ybar,
                                                   float *__restrict__ part, int64_t n, int win, int nsplit,
                                                   int64_t slice_pts, TcGrid gr)
@@ -591,38 +591,50 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
     const int64_t ps = (int64_t)blockIdx.y * slice_pts;
     const int64_t pe = min(n, ps + slice_pts);
     const int64_t ntl = ps < pe ? (pe - ps + TPT - 1) / TPT : 0;
-    const bool vec = (n % 4) == 0;
+    // VEC: n is a multiple of 4, so a lane's 4 points of a tile are one aligned 16-byte load
 
     // a tile's jets of the block's inputs and its B operands
     // ybar[c][32 og + 16 ot + r16][p0 + 4 g + s] (s = 0..3), in registers;
-    // the next tile's are loaded while the current one computes (zero past
-    // the slice end)
+    // the next tile's are loaded while the current one computes. Every load
+    // is issued at an in-range place; which values are real (not past the
+    // slice end or the block's inputs) is kept as masks and applied when the
+    // tile is used, a loop iteration later, so that no load is sunk into a
+    // branch (where the branches join the compiler would wait for every
+    // load in flight).
     constexpr int NQ = (TDI + 3) / 4;
     float pz[C][NQ];
     f4 py[C][2];
+    unsigned zmask = 0, ymask = 0;    // bit q: jet slot q real; bit s: point 4 g + s real
     auto load_tile = [&](int64_t t_) {
         const bool tok = t_ < ntl;
         const int64_t p0_ = ps + t_ * TPT;
         const int64_t p = p0_ + r16;
         const bool ok = tok && p < pe;
+        zmask = 0;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+        for (int q = 0; q < NQ; ++q) {
+            const int il = g + 4 * q;
+            const bool okq = ok && il < nin;
+            zmask |= okq ? 1u << q : 0u;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int il = g + 4 * q;
-                pz[c][q] = jet_sel<O0, O1, FIRST>(zin, c, i0 + il, win, n, p, ok && il < nin);
-            }
+            for (int c = 0; c < C; ++c) pz[c][q] = jet_in<O0, O1, FIRST>(zin, c, i0 + (okq ? il : 0), win, n, okq ? p : 0);
+        }
         const int64_t pg = p0_ + 4 * g;
+        ymask = 0;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) ymask |= (tok && pg + s4 < pe) ? 1u << s4 : 0u;
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int ot = 0; ot < 2; ++ot) {
-                const float *src = ybar + (int64_t)(c * N + 32 * og + 16 * ot + r16) * n + pg;
-                if (tok && vec && pg + 3 < pe) {
-                    py[c][ot] = *reinterpret_cast<const f4 *>(src);
+                const float *row = ybar + (int64_t)(c * N + 32 * og + 16 * ot + r16) * n;
+                if constexpr (VEC) {
+                    // n and pg are multiples of 4: pg <= n - 4 whenever pg < n
+                    const int64_t pc = tok ? min(pg, n - 4) : 0;
+                    py[c][ot] = *reinterpret_cast<const f4 *>(row + pc);
                 } else {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) py[c][ot][s] = (tok && pg + s < pe) ? src[s] : 0.f;
+                    for (int s4 = 0; s4 < 4; ++s4) py[c][ot][s4] = row[((ymask >> s4) & 1u) ? pg + s4 : 0];
                 }
             }
     };
@@ -635,13 +647,14 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                if (g + 4 * q < TDI) L.z[c][g + 4 * q][r16] = pz[c][q];
+                if (g + 4 * q < TDI) L.z[c][g + 4 * q][r16] = ((zmask >> q) & 1u) ? pz[c][q] : 0.f;
         f4 yv[C][2];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            yv[c][0] = py[c][0];
-            yv[c][1] = py[c][1];
-        }
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) yv[c][ot][s4] = ((ymask >> s4) & 1u) ? py[c][ot][s4] : 0.f;
         load_tile(t + TPH);
         __builtin_amdgcn_wave_barrier();
         build_klist<TDJ>(L.z[0], lane, p0, pe, lo, inv_w, nb, r0s, cnts, nin);
@@ -848,7 +861,9 @@ hipError_t launch_dw_tc(ChanCfg ch, bool first, const float *zin, const float *y
     const size_t sh = dw_tc_lds_bytes(ls.nb);
     HRK_TC_CH_SWITCH(ch, {
         HRK_TC_N_SWITCH(ls.wout, {
-            auto kf = first ? k_dw_tc<O0, O1, true, NT16> : k_dw_tc<O0, O1, false, NT16>;
+            const bool vec = n % 4 == 0;
+            auto kf = first ? (vec ? k_dw_tc<O0, O1, true, NT16, true> : k_dw_tc<O0, O1, true, NT16, false>)
+                            : (vec ? k_dw_tc<O0, O1, false, NT16, true> : k_dw_tc<O0, O1, false, NT16, false>);
             const hipError_t e = raise_lds(first ? 1 : 0, (const void *)kf, sh);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kf, grid, dim3(TNT), sh, st, zin, ybar, part, n, ls.win, nsplit, slice, gr);
