@@ -228,16 +228,29 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_fwd_tc(const float *_
         for (int ch = 0; ch < nchunk; ++ch) {
             const int i0 = ch * TKJ;
             // the chunk's jets: lane (r16 = point, g) loads inputs g, g + 4, ..
+            // Past the last point or the layer's inputs the lane reads point 0
+            // / input 0 instead and no value is selected: the K list takes
+            // neither (build_klist masks them), and a padding point's row of
+            // the products is its own and never stored. So each load goes
+            // straight to its register, all are issued before the first LDS
+            // write (the scheduling barrier), and one wait covers them.
             {
                 const int64_t p = p0 + r16;
                 const bool ok = p < n;
+                float zr[C][TKJ / 4];
 #pragma unroll
                 for (int c = 0; c < C; ++c)
 #pragma unroll
                     for (int q = 0; q < TKJ / 4; ++q) {
                         const int il = g + 4 * q;
-                        L.z[c][il][r16] = jet_sel<O0, O1, FIRST>(zin, c, i0 + il, win, n, p, ok && il < nin);
+                        const bool okq = ok && il < nin;
+                        zr[c][q] = jet_in<O0, O1, FIRST>(zin, c, i0 + (okq ? il : 0), win, n, okq ? p : 0);
                     }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int q = 0; q < TKJ / 4; ++q) L.z[c][g + 4 * q][r16] = zr[c][q];
             }
             __builtin_amdgcn_wave_barrier();
             build_klist<TKJ>(L.z[0], lane, p0, n, lo, inv_w, nb, r0s, cnts, nin);
