@@ -399,6 +399,10 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
     const int64_t tstride = (int64_t)gridDim.x * TW;
     // a chunk's jets in registers, the next chunk's loaded during the current one
     float pz[C][TKJ / 4];
+    // Past the last point (or the last tile) a lane reads point 0 and keeps
+    // that value: the K list never takes such a point, and its column of the
+    // products, its adjoint terms and its sums are its own and never stored.
+    // Without a value select each load lands in its own register.
     auto load_chunk = [&](int64_t tl, int chn) {
         const int64_t p = tl * TPT + r16;
         const bool ok = tl < ntiles && p < n;
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int q = 0; q < TKJ / 4; ++q)
-                pz[c][q] = jet_sel<O0, O1, false>(zin, c, chn * TKJ + g + 4 * q, win, n, p, ok);
+                pz[c][q] = jet_in<O0, O1, false>(zin, c, chn * TKJ + g + 4 * q, win, n, ok ? p : 0);
     };
     load_chunk((int64_t)blockIdx.x * TW + wv, 0);
 
@@ -425,8 +429,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                     {
-                        const float v = ybar[(int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + (pl_ok ? pl : 0)];
-                        yb[c][sg][q] = pl_ok ? v : 0.f;
+                        yb[c][sg][q] = ybar[(int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + (pl_ok ? pl : 0)];
                     }
 
 #pragma unroll 1
