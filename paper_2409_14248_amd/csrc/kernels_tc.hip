@@ -675,57 +675,74 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
         __builtin_amdgcn_wave_barrier();
         build_klist<TDJ>(L.z[0], lane, p0, pe, lo, inv_w, nb, r0s, cnts, nin);
         __builtin_amdgcn_wave_barrier();
-        const int tot = write_entries<TDJ>(L.ent, lane, r0s, cnts);
+        // the same count in every lane: a scalar, so the loops below branch
+        // uniformly
+        const int tot = __builtin_amdgcn_readfirstlane(write_entries<TDJ>(L.ent, lane, r0s, cnts));
         __builtin_amdgcn_wave_barrier();
         const int nblk = (tot + 15) / 16;
-#pragma unroll 1
-        for (int eb = 0; eb < nblk; ++eb) {
-            const int em = eb * 16 + r16;              // this lane's A row (entry)
-            const bool em_ok = em < tot;
-            int il = 0, b = 0;
-            if (em_ok) {
-                const int en = L.ent[em];
-                il = en >> 8;
-                b = en & 0xFF;
-            }
-            const double2 kn = knots[b];
-            f4 acc[2] = {(f4){0.f, 0.f, 0.f, 0.f}, (f4){0.f, 0.f, 0.f, 0.f}};
-            // features of step s (point 4 g + s); the next step's are computed
-            // after this step's MFMAs are issued
-            auto comp_a = [&](int s, float *A) {
-                const int pt = 4 * g + s;
-                float zj[C];
+        // this lane's A row of entry block eb_ (entry eb_*16 + r16; past tot
+        // the last entry, multiplied as zero)
+        struct Ent {
+            int il;
+            double2 kn;
+            bool ok;
+        };
+        auto ent_of = [&](int eb_) {
+            const int em = eb_ * 16 + r16;
+            const int en = L.ent[min(em, tot - 1)];
+            return Ent{en >> 8, knots[en & 0xFF], em < tot};
+        };
+        // features of step s (point 4 g + s) of an entry block
+        auto comp_a = [&](const Ent &E, int s, float *A) {
+            const int pt = 4 * g + s;
+            float zj[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) zj[c] = L.z[c][il][pt];
-                double v0, v1, v2;
-                bump3d(kn, zj[0], inv_wd, v0, v1, v2);
+            for (int c = 0; c < C; ++c) zj[c] = L.z[c][E.il][pt];
+            double v0, v1, v2;
+            bump3d(E.kn, zj[0], inv_wd, v0, v1, v2);
 #pragma unroll
-                for (int c = 0; c < C; ++c) A[c] = em_ok ? feature<O0, O1>(c, v0, v1, v2, zj) : 0.f;
-            };
+            for (int c = 0; c < C; ++c) A[c] = E.ok ? feature<O0, O1>(c, v0, v1, v2, zj) : 0.f;
+        };
+        if (nblk > 0) {
+            // one software pipeline over every step of every entry block: the
+            // features of the next step (of the next block, after a block's
+            // last step) are computed while the current step's MFMAs run
+            Ent cur = ent_of(0);
             float A0[C], A1[C];
-            comp_a(0, A0);
+            comp_a(cur, 0, A0);
+#pragma unroll 1
+            for (int eb = 0; eb < nblk; ++eb) {
+                f4 acc[2] = {(f4){0.f, 0.f, 0.f, 0.f}, (f4){0.f, 0.f, 0.f, 0.f}};
+                Ent nxt = cur;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                float *Ac = (s & 1) ? A1 : A0;
-                float *An = (s & 1) ? A0 : A1;
+                for (int s = 0; s < 4; ++s) {
+                    float *Ac = (s & 1) ? A1 : A0;
+                    float *An = (s & 1) ? A0 : A1;   // after step 3: A0, the next block's step 0
 #pragma unroll
-                for (int c = 0; c < C; ++c)
+                    for (int c = 0; c < C; ++c)
 #pragma unroll
-                    for (int ot = 0; ot < 2; ++ot)
-                        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[c], yv[c][ot][s], acc[ot], 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);
-                if (s < 3) comp_a(s + 1, An);
-            }
-            // acc[ot][r] = D[entry eb*16 + 4 g + r][output 16 ot + r16]
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int e = eb * 16 + 4 * g + r;
-                if (e < tot) {
-                    const int en = L.ent[e];
-                    const int row = (en >> 8) * nb + (en & 0xFF);
-#pragma unroll
-                    for (int ot = 0; ot < 2; ++ot) grad[row * 32 + 16 * ot + r16] += acc[ot][r];
+                        for (int ot = 0; ot < 2; ++ot)
+                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[c], yv[c][ot][s], acc[ot], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (s < 3) {
+                        comp_a(cur, s + 1, An);
+                    } else if (eb + 1 < nblk) {
+                        nxt = ent_of(eb + 1);
+                        comp_a(nxt, 0, An);
+                    }
                 }
+                // acc[ot][r] = D[entry eb*16 + 4 g + r][output 16 ot + r16]
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = eb * 16 + 4 * g + r;
+                    if (e < tot) {
+                        const int en = L.ent[e];
+                        const int row = (en >> 8) * nb + (en & 0xFF);
+#pragma unroll
+                        for (int ot = 0; ot < 2; ++ot) grad[row * 32 + 16 * ot + r16] += acc[ot][r];
+                    }
+                }
+                cur = nxt;
             }
         }
         __builtin_amdgcn_wave_barrier();
