@@ -570,7 +570,7 @@ constexpr int TDI = 6;              // inputs per gradient block
 constexpr int TDJ = 8;              // lane-group capacity of the K list builder (>= TDI)
 
 template <int O0, int O1>
-struct TcDwLds {
+struct alignas(16) TcDwLds {
     static constexpr int C = 1 + O0 + O1;
     float z[C][TDI][TPT];
     unsigned short ent[TDI * MAXNB];
@@ -692,57 +692,72 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
             const int en = L.ent[min(em, tot - 1)];
             return Ent{en >> 8, knots[en & 0xFF], em < tot};
         };
-        // features of step s (point 4 g + s) of an entry block
-        auto comp_a = [&](const Ent &E, int s, float *A) {
-            const int pt = 4 * g + s;
-            float zj[C];
+        // features of the 4 steps (points 4 g + s) of an entry block: the
+        // lane's 4 points of each channel are one 16-byte LDS read, and the 4
+        // FP64 basis evaluations are independent of each other
+        auto comp_blk = [&](const Ent &E, float (*A)[C]) {
+            f4 zz[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) zj[c] = L.z[c][E.il][pt];
-            double v0, v1, v2;
-            bump3d(E.kn, zj[0], inv_wd, v0, v1, v2);
+            for (int c = 0; c < C; ++c) zz[c] = *reinterpret_cast<const f4 *>(&L.z[c][E.il][4 * g]);
 #pragma unroll
-            for (int c = 0; c < C; ++c) A[c] = E.ok ? feature<O0, O1>(c, v0, v1, v2, zj) : 0.f;
+            for (int s = 0; s < 4; ++s) {
+                float zj[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) zj[c] = zz[c][s];
+                double v0, v1, v2;
+                bump3d(E.kn, zj[0], inv_wd, v0, v1, v2);
+#pragma unroll
+                for (int c = 0; c < C; ++c) A[s][c] = E.ok ? feature<O0, O1>(c, v0, v1, v2, zj) : 0.f;
+            }
         };
         if (nblk > 0) {
-            // one software pipeline over every step of every entry block: the
-            // features of the next step (of the next block, after a block's
-            // last step) are computed while the current step's MFMAs run
+            // one software pipeline over the entry blocks: the next block's
+            // features are computed while the current block's products run,
+            // then the current block's gradient rows are read, added to and
+            // written (the K list holds each (input, row) once, so the 4 rows
+            // of a lane are distinct and all reads may precede the writes)
             Ent cur = ent_of(0);
-            float A0[C], A1[C];
-            comp_a(cur, 0, A0);
+            float Ac[4][C], An[4][C];
+            comp_blk(cur, Ac);
 #pragma unroll 1
             for (int eb = 0; eb < nblk; ++eb) {
                 f4 acc[2] = {(f4){0.f, 0.f, 0.f, 0.f}, (f4){0.f, 0.f, 0.f, 0.f}};
-                Ent nxt = cur;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    float *Ac = (s & 1) ? A1 : A0;
-                    float *An = (s & 1) ? A0 : A1;   // after step 3: A0, the next block's step 0
+                for (int s = 0; s < 4; ++s)
 #pragma unroll
                     for (int c = 0; c < C; ++c)
 #pragma unroll
                         for (int ot = 0; ot < 2; ++ot)
-                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[c], yv[c][ot][s], acc[ot], 0, 0, 0);
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (s < 3) {
-                        comp_a(cur, s + 1, An);
-                    } else if (eb + 1 < nblk) {
-                        nxt = ent_of(eb + 1);
-                        comp_a(nxt, 0, An);
-                    }
-                }
+                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[s][c], yv[c][ot][s], acc[ot], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
                 // acc[ot][r] = D[entry eb*16 + 4 g + r][output 16 ot + r16]
+                const int eq = eb * 16 + 4 * g;
+                int rw[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int e = eb * 16 + 4 * g + r;
-                    if (e < tot) {
-                        const int en = L.ent[e];
-                        const int row = (en >> 8) * nb + (en & 0xFF);
-#pragma unroll
-                        for (int ot = 0; ot < 2; ++ot) grad[row * 32 + 16 * ot + r16] += acc[ot][r];
-                    }
+                    const int en = L.ent[eq + r];
+                    rw[r] = eq + r < tot ? (en >> 8) * nb + (en & 0xFF) : 0;
                 }
-                cur = nxt;
+                const bool more = eb + 1 < nblk;
+                if (more) {
+                    cur = ent_of(eb + 1);
+                    comp_blk(cur, An);
+                }
+                float old[4][2];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int ot = 0; ot < 2; ++ot) old[r][ot] = grad[rw[r] * 32 + 16 * ot + r16];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (eq + r < tot)
+#pragma unroll
+                        for (int ot = 0; ot < 2; ++ot) grad[rw[r] * 32 + 16 * ot + r16] = old[r][ot] + acc[ot][r];
+                if (more)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+#pragma unroll
+                        for (int c = 0; c < C; ++c) Ac[s][c] = An[s][c];
             }
         }
         __builtin_amdgcn_wave_barrier();
