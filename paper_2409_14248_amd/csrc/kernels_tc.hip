@@ -106,6 +106,16 @@ __device__ __forceinline__ float jet_sel(const float *__restrict__ zin, int c, i
     return ok ? v : 0.f;
 }
 
+// lo = min(lo, lo of the lane M below), hi likewise with max, within a DPP
+// row of 16 lanes (row_shr:M; a lane whose source lies before the row start
+// keeps its own value)
+template <int M>
+__device__ __forceinline__ void row_shr_minmax(int &lo, int &hi)
+{
+    lo = min(lo, __builtin_amdgcn_update_dpp(lo, lo, 0x110 + M, 0xf, 0xf, false));
+    hi = max(hi, __builtin_amdgcn_update_dpp(hi, hi, 0x110 + M, 0xf, 0xf, false));
+}
+
 // Build the K list of the tile's chunk of inputs [i0, i0 + TKJ): each lane
 // group g (16 lanes, one per point) takes inputs g, g + 4, g + 8, g + 12 and
 // reduces the window starts over the tile's live points; then every lane
@@ -125,12 +135,14 @@ __device__ __forceinline__ void build_klist(const float (*zv)[TPT], int lane, in
         const bool live = in_ok && pt_ok && !(zt <= -1.5f) && !(zt >= 0.5f * (float)nb);
         const int qa = (int)fminf(fmaxf(2.f * zt, 0.f), (float)(nb - 4));
         int lo_q = live ? qa : 1 << 20, hi_q = live ? qa : -1;
-#pragma unroll
-        for (int m = 1; m < 16; m <<= 1) {
-            lo_q = min(lo_q, __shfl_xor(lo_q, m, 16));
-            hi_q = max(hi_q, __shfl_xor(hi_q, m, 16));
-        }
-        if (p == 0) {
+        // min and max over the 16 lanes (one DPP row): after shifts by 1, 2,
+        // 4 and 8 lanes within the row, lane 15 has seen every lane of it (a
+        // lane whose source would lie before the row start keeps its value)
+        row_shr_minmax<1>(lo_q, hi_q);
+        row_shr_minmax<2>(lo_q, hi_q);
+        row_shr_minmax<4>(lo_q, hi_q);
+        row_shr_minmax<8>(lo_q, hi_q);
+        if (p == 15) {
             r0s[il] = hi_q < 0 ? 0 : lo_q;
             cnts[il] = hi_q < 0 ? 0 : min(hi_q + 3, nb - 1) - lo_q + 1;
         }
@@ -573,7 +585,7 @@ template <int O0, int O1>
 struct alignas(16) TcDwLds {
     static constexpr int C = 1 + O0 + O1;
     float z[C][TDI][TPT];
-    unsigned short ent[TDI * MAXNB];
+    unsigned short ent[TDI * MAXNB];    // entry blocks of 16 (TDI * MAXNB is a multiple of 16)
 };
 
 template <int O0, int O1, bool FIRST, int NT16, bool VEC>
@@ -721,6 +733,13 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
             comp_blk(cur, Ac);
 #pragma unroll 1
             for (int eb = 0; eb < nblk; ++eb) {
+                // this lane's 4 accumulator entries (one 8-byte read; past tot
+                // unused) and its entry of the next block, read before the
+                // products so that their latency is hidden behind them
+                const int eq = eb * 16 + 4 * g;
+                const uint2 e4 = *reinterpret_cast<const uint2 *>(&L.ent[eq]);
+                const bool more = eb + 1 < nblk;
+                const int en_nx = L.ent[min((eb + 1) * 16 + r16, tot - 1)];
                 f4 acc[2] = {(f4){0.f, 0.f, 0.f, 0.f}, (f4){0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -731,16 +750,15 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
                             acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ac[s][c], yv[c][ot][s], acc[ot], 0, 0, 0);
                 __builtin_amdgcn_sched_barrier(0);
                 // acc[ot][r] = D[entry eb*16 + 4 g + r][output 16 ot + r16]
-                const int eq = eb * 16 + 4 * g;
                 int rw[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int en = L.ent[eq + r];
+                    const int en = (int)((r < 2 ? e4.x : e4.y) >> (16 * (r & 1))) & 0xFFFF;
                     rw[r] = eq + r < tot ? (en >> 8) * nb + (en & 0xFF) : 0;
                 }
-                const bool more = eb + 1 < nblk;
                 if (more) {
-                    cur = ent_of(eb + 1);
+                    const int em = (eb + 1) * 16 + r16;
+                    cur = Ent{en_nx >> 8, knots[en_nx & 0xFF], em < tot};
                     comp_blk(cur, An);
                 }
                 float old[4][2];
