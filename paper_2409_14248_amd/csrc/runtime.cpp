@@ -206,10 +206,12 @@ bool tc_enabled()
 // stage on the FP32 steps (ms per launch, sets ordered along the curve):
 //  - 32-output layers (c2): never: the point ordering alone (0.12 ms for
 //    65,536 + 4,096 points) costs more than they save;
-//  - 64 outputs (c3): forward (0.61 against 1.33) and weight gradient (1.52
-//    against 1.89), not the input bars (1.95 against 1.59);
-//  - 128 outputs (c4): every stage (forward 7.0 against 18.2, input bars
-//    13.3 against 20.9, weight gradient 19.2 against 24.3).
+//  - 64 outputs (c3): forward (0.61 against 1.33) and weight gradient (1.05
+//    to 1.20 against 1.89), not the input bars (1.55 and 1.80 for the two
+//    hidden layers against 1.60 and 1.60: the second layer's K lists are
+//    longer);
+//  - 128 outputs (c4): every stage (forward 6.1 against 18.2, input bars
+//    11.5 against 20.9, weight gradient 15.7 against 24.3).
 // stage: 'f' forward, 'x' input bars, 'w' weight gradient.
 bool use_tc(const NetInfo &ni, int l, char stage)
 {
