@@ -288,7 +288,6 @@ def main():
         "flops_per_launch": f_live, "launch_ms": round(per_launch_ms, 5),
         "kernel_share": round(dms / prof_steps / total_ms, 3),
         "achieved_dense_equivalent": round(achieved_dense, 3),
-        "frac_dense_equivalent": round(achieved_dense / peak, 4),
         "dense_equivalent_flops_per_launch": f_dense,
     }
     step_flops_live = sum(live.values())
