@@ -591,7 +591,7 @@ struct alignas(16) TcDwLds {
 template <int O0, int O1, bool FIRST, int NT16, bool VEC>
 __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin, const float *__restrict__ ybar,
                                                   float *__restrict__ part, int64_t n, int win, int nsplit,
-                                                  int64_t slice_pts, TcGrid gr)
+                                                  int64_t slice_pts, int nib, bool xcd_map, TcGrid gr)
 {
     constexpr int C = 1 + O0 + O1;
     constexpr int N = 16 * NT16;
@@ -609,14 +609,28 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
     const int nb = gr.nb;
     const float inv_w = gr.inv_w, lo = gr.lo;
     const double inv_wd = gr.inv_w_d;
-    const int i0 = blockIdx.x * TDI;
+    // this block's input group and point slice. Blocks are dealt to the 8
+    // XCDs in turn (block b to XCD b % 8); with xcd_map every input group of
+    // a slice runs on one XCD, one after the other in its dispatch order, so
+    // that the slice's bars, which each group reads, are shared in that
+    // XCD's L2 (nsplit is then a multiple of 8)
+    int ib, sl;
+    if (xcd_map) {
+        const int k = (int)(blockIdx.x >> 3);
+        ib = k % nib;
+        sl = (k / nib) * 8 + (int)(blockIdx.x & 7);
+    } else {
+        ib = (int)(blockIdx.x % nib);
+        sl = (int)(blockIdx.x / nib);
+    }
+    const int i0 = ib * TDI;
     const int nin = min(TDI, win - i0);
     const int rows = nin * nb;
     float *grad = dsm + (size_t)wv * TDI * nb * 32;        // [row][32]
     if (threadIdx.x < nb) knots[threadIdx.x] = make_double2(gr.s[threadIdx.x], gr.e[threadIdx.x]);
     for (int e = lane; e < TDI * nb * 32; e += 64) grad[e] = 0.f;
     __syncthreads();
-    const int64_t ps = (int64_t)blockIdx.y * slice_pts;
+    const int64_t ps = (int64_t)sl * slice_pts;
     const int64_t pe = min(n, ps + slice_pts);
     const int64_t ntl = ps < pe ? (pe - ps + TPT - 1) / TPT : 0;
     // VEC: n is a multiple of 4, so a lane's 4 points of a tile are one aligned 16-byte load
@@ -783,7 +797,7 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
     __syncthreads();
     // the slice's partial rows: the tile phases of each output group summed
     // in wave order
-    float *dst = part + (int64_t)blockIdx.y * ((int64_t)win * nb * N) + (int64_t)i0 * nb * N;
+    float *dst = part + (int64_t)sl * ((int64_t)win * nb * N) + (int64_t)i0 * nb * N;
     for (int e = threadIdx.x; e < rows * N; e += TNT) {
         const int row = e / N, j = e % N;
         const int o = j / 32, jj = j % 32;
@@ -904,15 +918,41 @@ hipError_t raise_lds(int, const void *kf, size_t bytes)
     return hipSuccess;
 }
 
+namespace {
+// blocks of the weight-gradient kernel one XCD holds at a time: two per CU
+int dw_xcd_slots()
+{
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+            cus = 256;
+        cached = 2 * (cus / 8);
+    }
+    return cached;
+}
+}  // namespace
+
 int dw_tc_splits(int64_t n, LayerShape ls)
 {
     if (n <= 0) return 0;
-    // two rounds of two blocks per CU over the input groups and point
-    // slices (rounded down, so the last round is not a sliver), with at
-    // least 256 points per slice
     const int64_t groups = (ls.win + TDI - 1) / TDI;
-    const int64_t s = std::max<int64_t>(1, 1024 / groups);
-    const int64_t maxs = std::max<int64_t>(1, n / 256);
+    const int64_t maxs = std::max<int64_t>(1, n / 256);     // at least 256 points per slice
+    // XCD-aware (a multiple of 8 slices, every group of a slice on one XCD):
+    // the fewest slices per XCD, m, that give at least two rounds of the
+    // XCD's blocks with the last round at least 95% full, at 2,048 points
+    // per slice or more (a block's partial rows stay small beside its reads)
+    const int64_t slots = dw_xcd_slots();
+    for (int64_t m = 1; m <= 64 && 8 * m <= n / 2048; ++m) {
+        const int64_t blocks = groups * m;
+        if (blocks < 2 * slots) continue;
+        const int64_t rounds = (blocks + slots - 1) / slots;
+        if (blocks * 100 >= rounds * slots * 95) return (int)(8 * m);
+    }
+    // otherwise two rounds of two blocks per CU over the input groups and
+    // point slices (rounded down, so the last round is not a sliver)
+    const int64_t s = std::max<int64_t>(1, 8 * slots / groups);
     return (int)std::max<int64_t>(1, std::min<int64_t>(std::min(s, maxs), 4096));
 }
 
@@ -923,7 +963,9 @@ hipError_t launch_dw_tc(ChanCfg ch, bool first, const float *zin, const float *y
     if (!tc_supported(ch, ls, 3, 4, first) || nsplit < 1) return hipErrorInvalidValue;
     int64_t slice = (n + nsplit - 1) / nsplit;
     slice = (slice + TPT - 1) / TPT * TPT;
-    const dim3 grid((unsigned)((ls.win + TDI - 1) / TDI), (unsigned)nsplit);
+    const int nib = (ls.win + TDI - 1) / TDI;
+    const dim3 grid((unsigned)(nib * nsplit));
+    const bool xcd_map = nsplit % 8 == 0;
     const size_t sh = dw_tc_lds_bytes(ls.nb);
     HRK_TC_CH_SWITCH(ch, {
         HRK_TC_N_SWITCH(ls.wout, {
@@ -932,7 +974,8 @@ hipError_t launch_dw_tc(ChanCfg ch, bool first, const float *zin, const float *y
                             : (vec ? k_dw_tc<O0, O1, false, NT16, true> : k_dw_tc<O0, O1, false, NT16, false>);
             const hipError_t e = raise_lds(first ? 1 : 0, (const void *)kf, sh);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kf, grid, dim3(TNT), sh, st, zin, ybar, part, n, ls.win, nsplit, slice, gr);
+            hipLaunchKernelGGL(kf, grid, dim3(TNT), sh, st, zin, ybar, part, n, ls.win, nsplit, slice, nib, xcd_map,
+                               gr);
         });
     });
     return hipGetLastError();
