@@ -414,7 +414,9 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
     // Past the last point (or the last tile) a lane reads point 0 and keeps
     // that value: the K list never takes such a point, and its column of the
     // products, its adjoint terms and its sums are its own and never stored.
-    // Without a value select each load lands in its own register.
+    // Without a value select each load lands in its own register. Jets and
+    // bars stream through once per pass (non-temporal loads), so that L2
+    // keeps the weight rows the entry blocks read.
     auto load_chunk = [&](int64_t tl, int chn) {
         const int64_t p = tl * TPT + r16;
         const bool ok = tl < ntiles && p < n;
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int q = 0; q < TKJ / 4; ++q)
-                pz[c][q] = jet_in<O0, O1, false>(zin, c, chn * TKJ + g + 4 * q, win, n, ok ? p : 0);
+                pz[c][q] = __builtin_nontemporal_load(zin + (int64_t)(c * win + chn * TKJ + g + 4 * q) * n + (ok ? p : 0));
     };
     load_chunk((int64_t)blockIdx.x * TW + wv, 0);
 
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                     {
-                        yb[c][sg][q] = ybar[(int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + (pl_ok ? pl : 0)];
+                        yb[c][sg][q] = __builtin_nontemporal_load(ybar + (int64_t)(c * N + j0 + 16 * sg + 4 * g + q) * n + (pl_ok ? pl : 0));
                     }
 
 #pragma unroll 1
