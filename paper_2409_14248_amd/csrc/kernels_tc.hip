@@ -81,7 +81,9 @@ __device__ __forceinline__ float feature(int c, double v0, double v1, double v2,
 // Jets of a chunk's input il at point p: a hidden layer reads its saved
 // jets [C][win][n]; the first layer the coordinates x [n][2] (input il is
 // coordinate il, with unit first derivative along its own direction).
-template <int O0, int O1, bool FIRST>
+// NT: a non-temporal load (the value streams through once, so L2 keeps what
+// is re-read, such as weight rows).
+template <int O0, int O1, bool FIRST, bool NT = false>
 __device__ __forceinline__ float jet_in(const float *__restrict__ zin, int c, int i, int win, int64_t n, int64_t p)
 {
     if constexpr (FIRST) {
@@ -90,6 +92,8 @@ __device__ __forceinline__ float jet_in(const float *__restrict__ zin, int c, in
         if (c == CH::X) return i == 0 ? 1.f : 0.f;
         if (c == CH::Y) return i == 1 ? 1.f : 0.f;
         return 0.f;
+    } else if constexpr (NT) {
+        return __builtin_nontemporal_load(zin + (int64_t)(c * win + i) * n + p);
     } else {
         return zin[(int64_t)(c * win + i) * n + p];
     }
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int q = 0; q < TKJ / 4; ++q)
-                pz[c][q] = __builtin_nontemporal_load(zin + (int64_t)(c * win + chn * TKJ + g + 4 * q) * n + (ok ? p : 0));
+                pz[c][q] = jet_in<O0, O1, false, true>(zin, c, chn * TKJ + g + 4 * q, win, n, ok ? p : 0);
     };
     load_chunk((int64_t)blockIdx.x * TW + wv, 0);
 
