@@ -946,16 +946,17 @@ int dw_tc_splits(int64_t n, LayerShape ls)
     const int64_t groups = (ls.win + TDI - 1) / TDI;
     const int64_t maxs = std::max<int64_t>(1, n / 256);     // at least 256 points per slice
     // XCD-aware (a multiple of 8 slices, every group of a slice on one XCD):
-    // the fewest slices per XCD, m, that give at least 8 rounds of the XCD's
+    // the fewest slices per XCD, m, that give at least 12 rounds of the XCD's
     // blocks (else at least 2) with the last round at least 95% full, at
     // 2,048 points per slice or more (a block's partial rows stay small
     // beside its reads). On the 128-wide hidden layers of 1,048,576 points
-    // (22 groups, 64 blocks per XCD at a time) 9 to 10 rounds took 14.7 to
-    // 14.9 ms per launch, 5 rounds 15.1, 3 rounds 16.1 (smaller slices keep
-    // the groups of a slice closer together in time, so more of their reads
-    // of the bars hit in L2)
+    // (22 groups, 64 blocks per XCD at a time) 13 to 17 rounds took 14.5 ms
+    // per launch, 9 to 10 rounds 14.7 to 14.9, 5 rounds 15.1, 3 rounds 16.1
+    // (smaller slices keep the groups of a slice closer together in time, so
+    // more of their reads of the bars hit in L2; the slices' partial rows
+    // grow with their number, 1.5 MB each there)
     const int64_t slots = dw_xcd_slots();
-    for (const int64_t min_rounds : {8, 2})
+    for (const int64_t min_rounds : {12, 2})
         for (int64_t m = 1; m <= 64 && 8 * m <= n / 2048; ++m) {
             const int64_t blocks = groups * m;
             if (blocks < min_rounds * slots) continue;
