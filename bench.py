@@ -80,6 +80,7 @@ def layer_flops(net, C, n, live=False):
         out[f"dw_l{l}"] = f
         if l > 0:
             out[f"dx_l{l}"] = f
+            out[f"dwx_l{l}"] = 2 * f    # a 1-output layer's gradient and input bars in one launch
     return out
 
 

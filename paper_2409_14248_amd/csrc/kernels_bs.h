@@ -25,6 +25,11 @@ hipError_t launch_dx_bs32(ChanCfg ch, const float *zin, const float *ybar, const
                           int64_t n, LayerShape ls, const GridP<float> &g, int cu_blocks, int S,
                           hipStream_t st, const BatchMap &bm = BatchMap{});
 int dw_bs32_splits(int64_t n, LayerShape ls);
+// The weight-gradient slices of a 1-output layer (as launch_dw_bs32) and, in
+// the same pass over its jets, its input bars (as launch_dx_bs32).
+hipError_t launch_back_last(ChanCfg ch, const float *zin, const float *ybar, const float *W, float *zbar, float *part,
+                            int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, hipStream_t st,
+                            const BatchMap &bm = BatchMap{});
 hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float *ybar, float *part,
                           int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, int S,
                           hipStream_t st, const BatchMap &bm = BatchMap{}, int dw_ii_override = 0);

@@ -1061,39 +1061,16 @@ __global__ __launch_bounds__(NT) void k_fwd_last(const float *__restrict__ zin,
     }
 }
 
-// zbar[c][i][p] from ubar[c][p]; one thread per (point, input). With
-// S1..S3 the weighted sums of dv, d2v, d3v (the feature bars are w_r ubar_c):
+// The input bars of a point and input of a 1-output layer from its jets zj,
+// the output bars yb and the window sums P (window_sums): with
+// S1..S3 the weighted sums of dv, d2v, d3v (the feature bars are w_r ubar_c),
 //   zbar_U  = ubar_U S1 + sum_d [ubar_d S2 zd + ubar_dd (S3 zd^2 + S2 zdd)]
 //   zbar_d  = ubar_d S1 + 2 ubar_dd S2 zd,   zbar_dd = ubar_dd S1
 template <int O0, int O1>
-__global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
-                                                const float *__restrict__ ybar,
-                                                const float *__restrict__ W,
-                                                float *__restrict__ zbar, int64_t n, int win,
-                                                GridP<float> g, BatchMap bm)
+__device__ __forceinline__ void dx_last_bars(const float *zj, const float *yb, const float *P, float inv_w, float *zb)
 {
     using CH = Ch<O0, O1>;
     constexpr int C = CH::C;
-    constexpr int NP = C > 1 ? 4 : 2;
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (e >= n * win) return;
-    const int i = (int)(e / n);
-    const int64_t p = e % n;
-    if (bm.tile_inst) W += (int64_t)bm.tile_inst[p >> 7] * bm.w_stride;
-    const int nb = g.nb;
-    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
-    float zj[C], yb[C], zb[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        zj[c] = zin[((int64_t)c * win + i) * n + p];
-        yb[c] = ybar[(int64_t)c * n + p];
-    }
-    const float zt = zj[CH::U] * inv_w + zoff;
-    const int qa = window_k3(zt, nb);
-    const float *wr = W + i * nb + qa;
-    const float w4[4] = {wr[0], wr[1], wr[2], wr[3]};
-    float P[NP];
-    window_sums<NP>(zt, nan_carrier(zt), qa, w4, P);
     const float S1 = (-8.f * inv_w) * P[1];
     float z0 = yb[CH::U] * S1;
     if constexpr (C > 1) {
@@ -1119,6 +1096,41 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
         }
     }
     zb[CH::U] = z0;
+}
+
+// zbar[c][i][p] from ubar[c][p]; one thread per (point, input)
+// (dx_last_bars).
+template <int O0, int O1>
+__global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
+                                                const float *__restrict__ ybar,
+                                                const float *__restrict__ W,
+                                                float *__restrict__ zbar, int64_t n, int win,
+                                                GridP<float> g, BatchMap bm)
+{
+    using CH = Ch<O0, O1>;
+    constexpr int C = CH::C;
+    constexpr int NP = C > 1 ? 4 : 2;
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= n * win) return;
+    const int i = (int)(e / n);
+    const int64_t p = e % n;
+    if (bm.tile_inst) W += (int64_t)bm.tile_inst[p >> 7] * bm.w_stride;
+    const int nb = g.nb;
+    const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
+    float zj[C], yb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        zj[c] = zin[((int64_t)c * win + i) * n + p];
+        yb[c] = ybar[(int64_t)c * n + p];
+    }
+    const float zt = zj[CH::U] * inv_w + zoff;
+    const int qa = window_k3(zt, nb);
+    const float *wr = W + i * nb + qa;
+    const float w4[4] = {wr[0], wr[1], wr[2], wr[3]};
+    float P[NP];
+    window_sums<NP>(zt, nan_carrier(zt), qa, w4, P);
+    float zb[C];
+    dx_last_bars<O0, O1>(zj, yb, P, inv_w, zb);
 #pragma unroll
     for (int c = 0; c < C; ++c) zbar[((int64_t)c * win + i) * n + p] = zb[c];
 }
@@ -1128,21 +1140,27 @@ __global__ __launch_bounds__(NT) void k_dx_last(const float *__restrict__ zin,
 // (point, input) adds sum_c A_c ubar_c = t^4 ubar_U + t^3 u G1 + t^2 (u^2 -
 // 1/7) G2 with G1 = -8 iw sum_d (zd ubar_d + zdd ubar_dd) and
 // G2 = 56 iw^2 sum_d zd^2 ubar_dd.
+// DX: the same pass also writes the input bars zbar[c][i][p] of each point
+// it visits (what k_dx_last computes), so the layer's jets are read once for
+// both.
 constexpr int DL_SL = 8;   // point lanes per input
-template <int O0, int O1>
+// SL: point lanes per input (DL_SL, or 64 for DX, whose bar stores then
+// cover 64 consecutive points of one input per wave)
+template <int O0, int O1, bool DX, int SL = DL_SL>
 __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
                                                 const float *__restrict__ ybar,
                                                 float *__restrict__ part, int64_t n, int win,
-                                                int nsplit, GridP<float> g, BatchMap bm)
+                                                int nsplit, GridP<float> g, BatchMap bm,
+                                                const float *__restrict__ W, float *__restrict__ zbar)
 {
     using CH = Ch<O0, O1>;
     constexpr int C = CH::C;
-    constexpr int IB = NT / DL_SL;        // inputs per block
+    constexpr int IB = NT / SL;           // inputs per block
     __shared__ float sacc[NT][33];
     const int nb = g.nb;
     const float inv_w = g.inv_w, zoff = -g.lo * g.inv_w;
     const float k1 = -8.f * inv_w, k2 = 56.f * inv_w * inv_w;
-    const int li = threadIdx.x / DL_SL, sl = threadIdx.x % DL_SL;
+    const int li = threadIdx.x / SL, sl = threadIdx.x % SL;
     const int i = blockIdx.x * IB + li;
     const int split = blockIdx.y;
     const int64_t per = (n + nsplit - 1) / nsplit;
@@ -1151,15 +1169,16 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
         const int4 sl = bm.slices[split];
         ps = sl.y;
         pe = sl.z;
+        if (DX) W += (int64_t)sl.x * bm.w_stride;   // a slice lies within one instance
     }
     for (int b = 0; b < nb; ++b) sacc[threadIdx.x][b] = 0.f;
     if (i < win) {
         constexpr int U = 4;                    // points whose loads are in flight together
-        for (int64_t p0 = ps + sl; p0 < pe; p0 += U * DL_SL) {
+        for (int64_t p0 = ps + sl; p0 < pe; p0 += U * SL) {
             float zj[U][C], yb[U][C];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t p = p0 + (int64_t)u * DL_SL;
+                const int64_t p = p0 + (int64_t)u * SL;
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     zj[u][c] = p < pe ? zin[((int64_t)c * win + i) * n + p] : 0.f;
@@ -1168,7 +1187,7 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (p0 + (int64_t)u * DL_SL >= pe) break;
+                if (p0 + (int64_t)u * SL >= pe) break;
                 const float zt = zj[u][CH::U] * inv_w + zoff;
                 const float sn = nan_carrier(zt);
                 const int qa = window_k3(zt, nb);
@@ -1199,6 +1218,18 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
                     }
                     sacc[threadIdx.x][qa + r] += sum;
                 }
+                if constexpr (DX) {
+                    constexpr int NP = C > 1 ? 4 : 2;
+                    const int64_t p = p0 + (int64_t)u * SL;
+                    const float *wr = W + i * nb + qa;
+                    const float w4[4] = {wr[0], wr[1], wr[2], wr[3]};
+                    float P[NP];
+                    window_sums<NP>(zt, sn, qa, w4, P);
+                    float zb[C];
+                    dx_last_bars<O0, O1>(zj[u], yb[u], P, inv_w, zb);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) zbar[((int64_t)c * win + i) * n + p] = zb[c];
+                }
             }
         }
     }
@@ -1209,7 +1240,7 @@ __global__ __launch_bounds__(NT) void k_dw_last(const float *__restrict__ zin,
         const int i2 = blockIdx.x * IB + l2;
         if (i2 >= win) continue;
         float sum = 0.f;
-        for (int k = 0; k < DL_SL; ++k) sum += sacc[l2 * DL_SL + k][b];
+        for (int k = 0; k < SL; ++k) sum += sacc[l2 * SL + k][b];
         part[(int64_t)split * win * nb + i2 * nb + b] = sum;
     }
 }
@@ -1435,6 +1466,20 @@ static LayerShape dw_block_shape(LayerShape ls)
     return ls;
 }
 
+hipError_t launch_back_last(ChanCfg ch, const float *zin, const float *ybar, const float *W, float *zbar, float *part,
+                            int nsplit, int64_t n, LayerShape ls, const GridP<float> &g, hipStream_t st,
+                            const BatchMap &bm)
+{
+    if (n <= 0) return hipSuccess;
+    if (ls.wout != 1 || nsplit < 1) return hipErrorInvalidValue;
+    constexpr int SL = 64;
+    dim3 grid((unsigned)((ls.win + NT / SL - 1) / (NT / SL)), (unsigned)nsplit);
+    HRK_CH_SWITCH32(ch, {
+        k_dw_last<O0, O1, true, SL><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, nsplit, g, bm, W, zbar);
+    });
+    return hipGetLastError();
+}
+
 int dw_bs32_splits(int64_t n, LayerShape ls)
 {
     if (n <= 0) return 0;
@@ -1459,7 +1504,8 @@ hipError_t launch_dw_bs32(ChanCfg ch, bool first, const float *zin, const float 
     if (ls.wout == 1) {
         dim3 grid((unsigned)((ls.win + NT / DL_SL - 1) / (NT / DL_SL)), (unsigned)nsplit);
         HRK_CH_SWITCH32(ch, {
-            k_dw_last<O0, O1><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, nsplit, g, bm);
+            k_dw_last<O0, O1, false><<<grid, NT, 0, st>>>(zin, ybar, part, n, ls.win, nsplit, g, bm, nullptr,
+                                                          nullptr);
         });
         return hipGetLastError();
     }

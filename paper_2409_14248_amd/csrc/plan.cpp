@@ -273,6 +273,14 @@ int enqueue(const hrkan_plan *p, const PlanCfg &cfg, hipStream_t st)
             int64_t off = 0;
             for (int q = 1; q < l; ++q) off += (int64_t)ch.C() * ni.w[q] * n;
             const float *zin = l == 0 ? x : saved + off;
+            if (l > 0 && ls.wout == 1) {
+                // the 1-output layer's weight gradient and input bars in one pass
+                float *zbar = (ybar == bar0) ? bar1 : bar0;
+                PTRY(launch_back_last(ch, zin, ybar, p->W + p->woff[l], zbar, part + base[l] + (int64_t)slot0 * kn[l], nsl,
+                                      n, ls, g, st, bm));
+                ybar = zbar;
+                continue;
+            }
             PTRY(launch_dw_bs32(ch, l == 0, zin, ybar, part + base[l] + (int64_t)slot0 * kn[l], nsl, n, ls, g, bf16_terms(ni),
                                 st, bm, cfg.dw_ii));
             if (l == 0) break;

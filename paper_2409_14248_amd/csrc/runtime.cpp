@@ -568,6 +568,20 @@ int reverse_set(const NetInfo &ni, const T *const *W, const RevSet<T> &S, const 
         const int ns = dw_splits(ni, l, S.n);
         const T *zin = layer_input<T>(ni, S.ch.C(), l, S.x, S.saved, S.n);
         hipError_t e;
+        if constexpr (std::is_same<T, float>::value) {
+            // a 1-output layer below which there are layers: its weight
+            // gradient and input bars in one pass over its jets
+            if (l > 0 && ls.wout == 1 && use_bs32(ni, l)) {
+                T *zbar = (ybar == S.bar0) ? S.bar1 : S.bar0;
+                {
+                    ProfScope ps("dwx", l, st, bc);
+                    e = launch_back_last(S.ch, zin, ybar, W[l], zbar, part + off[l], ns, S.n, ls, g, st);
+                }
+                if (e != hipSuccess) return hip_fail(e, "last-layer gradient launch");
+                ybar = zbar;
+                continue;
+            }
+        }
         {
             ProfScope ps("dw", l, st, bc);
             T *dst = part + off[l];
