@@ -80,7 +80,6 @@ def layer_flops(net, C, n, live=False):
         out[f"dw_l{l}"] = f
         if l > 0:
             out[f"dx_l{l}"] = f
-            out[f"dwx_l{l}"] = 2 * f    # a 1-output layer's gradient and input bars in one launch
     return out
 
 
@@ -95,6 +94,9 @@ def kernel_flops(pr, C, live=False, merged=False):
             out[k] += v
         else:
             out[k + "_bc"] = v
+    # a 1-output layer's weight gradient and input bars run as one launch
+    for k in [k for k in out if k.startswith("dx_l")]:
+        out["dwx" + k[2:]] = out["dw" + k[2:]] + out[k]
     return out
 
 
@@ -291,7 +293,7 @@ def main():
         "achieved_dense_equivalent": round(achieved_dense, 3),
         "dense_equivalent_flops_per_launch": f_dense,
     }
-    step_flops_live = sum(live.values())
+    step_flops_live = sum(v for k, v in live.items() if not k.startswith("dwx"))
 
     # the same step with BF16 products on the same shapes
     compare = {}
