@@ -908,7 +908,8 @@ __global__ __launch_bounds__(NT) void k_dw_bs(const float *__restrict__ zin,
         int pp = wp;
         // wide layers with one point group: points in fours, so that the
         // next points' operands are prepared while earlier ones update
-        // (c3: 2.02 -> 1.93 ms per launch). Narrow layers keep pairs: the
+        // (Poisson [2,64,64,64,1], 262,144 points: 2.02 -> 1.93 ms per
+        // launch). Narrow layers keep pairs: the
         // registers of four points would halve the blocks per CU of their
         // smaller-LDS instances.
         if constexpr (NQ >= 16)
@@ -1457,8 +1458,9 @@ static DwTile dw_tile(LayerShape ls, int C, int ii_override = 0)
 // Output blocks of the weight-gradient launch: a layer of 64 or 128 outputs
 // is split over two blocks (grid z) of half the outputs each, which halves a
 // block's LDS gradient copy and staged bars (128 outputs: two blocks per CU
-// instead of one; c4 33.2 -> 24.5 ms, c3 1.99 -> 1.90 ms per launch), at the
-// cost of evaluating the features twice.
+// instead of one; 128 outputs over 1,048,576 points 33.2 -> 24.5 ms, 64
+// outputs over 262,144 points 1.99 -> 1.90 ms per launch), at the cost of
+// evaluating the features twice.
 static int dw_jsplit(LayerShape ls) { return ls.wout >= 64 ? 2 : 1; }
 static LayerShape dw_block_shape(LayerShape ls)
 {

@@ -204,14 +204,17 @@ bool tc_enabled()
 
 // Where the tile-coherent kernels beat the block-sparse ones, measured per
 // stage on the FP32 steps (ms per launch, sets ordered along the curve):
-//  - 32-output layers (c2): never: the point ordering alone (0.12 ms for
-//    65,536 + 4,096 points) costs more than they save;
-//  - 64 outputs (c3): forward (0.61 against 1.33) and weight gradient (1.05
-//    to 1.20 against 1.89), not the input bars (1.55 and 1.80 for the two
-//    hidden layers against 1.60 and 1.60: the second layer's K lists are
-//    longer);
-//  - 128 outputs (c4): every stage (forward 6.1 against 18.2, input bars
-//    11.5 against 20.9, weight gradient 15.7 against 24.3).
+//  - 32-output layers (Burgers [2,32,32,1], 65,536 + 4,096 points): never:
+//    the point ordering alone (0.12 ms) costs more than they save (at
+//    1,048,576 points they save 0.4 ms of 4.5 per step, the ordering costing
+//    0.24);
+//  - 64 outputs (Poisson [2,64,64,64,1], 262,144 points): forward (0.61
+//    against 1.33) and weight gradient (1.05 to 1.20 against 1.89), not the
+//    input bars (1.55 and 1.80 for the two hidden layers against 1.60 and
+//    1.60: the second layer's K lists are longer);
+//  - 128 outputs (Burgers [2,128,128,128,1], 1,048,576 points): every stage
+//    (forward 6.1 against 18.2, input bars 11.3 against 20.9, weight
+//    gradient 14.5 against 24.3).
 // stage: 'f' forward, 'x' input bars, 'w' weight gradient.
 bool use_tc(const NetInfo &ni, int l, char stage)
 {
