@@ -178,19 +178,21 @@ __device__ __forceinline__ int write_entries(unsigned short *ent, int lane, cons
     return tot;
 }
 
-// v', v'', v''' of bump b at FP32 input z, in FP64 (v[0] unused), for the
-// adjoint of the features; zero off the open support, a NaN input carried.
-__device__ __forceinline__ void bump_d123d(double2 kn, float z, double inv_w, double *v)
+// v', v'', v''' of bump b at FP32 input z (v[0] unused), for the adjoint of
+// the features in the input bars: the offsets of z to the knots, where FP32
+// would cancel, are taken in FP64 and rounded once; the polynomial in FP32
+// then costs a few FP32 units relative, below the FP32 rounding of the
+// input-bar sums it feeds. Zero off the open support, a NaN input carried.
+__device__ __forceinline__ void bump_d123f(double2 kn, float z, double inv_w, float *v)
 {
     const double zd = (double)z;
-    const double a = (zd - kn.x) * inv_w, be = (kn.y - zd) * inv_w;
-    const bool in = !(a <= 0.0) && !(be <= 0.0);
-    const double t = a * be, d = be - a, t2 = t * t;
-    const double w2 = inv_w * inv_w;
-    v[0] = 0.0;
-    v[1] = in ? (4.0 * inv_w) * (t2 * t) * d : 0.0;
-    v[2] = in ? (4.0 * w2) * t2 * (3.0 * d * d - 2.0 * t) : 0.0;
-    v[3] = in ? (24.0 * w2 * inv_w) * t * d * (d * d - 3.0 * t) : 0.0;
+    const float a = (float)((zd - kn.x) * inv_w), be = (float)((kn.y - zd) * inv_w);
+    const bool in = !(a <= 0.f) && !(be <= 0.f);
+    const float t = a * be, d = be - a, t2 = t * t;
+    v[0] = 0.f;
+    v[1] = in ? (float)(4.0 * inv_w) * (t2 * t) * d : 0.f;
+    v[2] = in ? (float)(4.0 * inv_w * inv_w) * t2 * (3.f * d * d - 2.f * t) : 0.f;
+    v[3] = in ? (float)(24.0 * inv_w * inv_w * inv_w) * t * d * (d * d - 3.f * t) : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -510,17 +512,17 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
                         const int e = eb * 16 + 4 * g + r;
                         const int en = L.ent[min(e, tot - 1)];
                         const int il = en >> 8, b = en & 0xFF;
-                        double zj[C], Ab[C], v[4], zd[C];
+                        float zj[C], Ab[C], v[4], zd[C];
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
-                            zj[c] = (double)L.z[c][il][r16];
-                            Ab[c] = (double)acc[c][r];
-                            zd[c] = 0.0;
+                            zj[c] = L.z[c][il][r16];
+                            Ab[c] = acc[c][r];
+                            zd[c] = 0.f;
                         }
-                        bump_d123d(knots[b], L.z[0][il][r16], inv_wd, v);
-                        features_adjoint<double, O0, O1>(v, zj, Ab, zd);
+                        bump_d123f(knots[b], zj[0], inv_wd, v);
+                        features_adjoint<float, O0, O1>(v, zj, Ab, zd);
 #pragma unroll
-                        for (int c = 0; c < C; ++c) L.tm[4 * g + r][c][r16] = e < tot ? (float)zd[c] : 0.f;
+                        for (int c = 0; c < C; ++c) L.tm[4 * g + r][c][r16] = e < tot ? zd[c] : 0.f;
                     }
                     __builtin_amdgcn_wave_barrier();
                     // per (channel, point): the block's entries in order, one
