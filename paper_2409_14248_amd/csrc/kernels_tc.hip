@@ -78,6 +78,32 @@ __device__ __forceinline__ float feature(int c, double v0, double v1, double v2,
     return (float)(v2 * ((double)zj[CH::Y] * (double)zj[CH::Y]) + v1 * (double)zj[CH::YY]);
 }
 
+// The same basis values and features with the offsets of z to the knots in
+// FP64, rounded once, and the rest in FP32 (a few FP32 units relative): for
+// the weight gradient, whose features enter only that layer's gradient sums
+// (FP32), not the later layers.
+__device__ __forceinline__ void bump3f(double2 kn, float z, double inv_w, float &v0, float &v1, float &v2)
+{
+    const double zd = (double)z;
+    const float a = (float)((zd - kn.x) * inv_w), be = (float)((kn.y - zd) * inv_w);
+    const bool in = !(a <= 0.f) && !(be <= 0.f);
+    const float t = a * be, d = be - a, t2 = t * t;
+    v0 = in ? t2 * t2 : 0.f;
+    v1 = in ? (float)(4.0 * inv_w) * (t2 * t) * d : 0.f;
+    v2 = in ? (float)(4.0 * inv_w * inv_w) * t2 * (3.f * d * d - 2.f * t) : 0.f;
+}
+
+template <int O0, int O1>
+__device__ __forceinline__ float feature_f(int c, float v0, float v1, float v2, const float *zj)
+{
+    using CH = Ch<O0, O1>;
+    if (c == CH::U) return v0;
+    if (c == CH::X) return v1 * zj[CH::X];
+    if (c == CH::XX) return v2 * (zj[CH::X] * zj[CH::X]) + v1 * zj[CH::XX];
+    if (c == CH::Y) return v1 * zj[CH::Y];
+    return v2 * (zj[CH::Y] * zj[CH::Y]) + v1 * zj[CH::YY];
+}
+
 // Jets of a chunk's input il at point p: a hidden layer reads its saved
 // jets [C][win][n]; the first layer the coordinates x [n][2] (input il is
 // coordinate il, with unit first derivative along its own direction).
@@ -738,10 +764,10 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
                 float zj[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) zj[c] = zz[c][s];
-                double v0, v1, v2;
-                bump3d(E.kn, zj[0], inv_wd, v0, v1, v2);
+                float v0, v1, v2;
+                bump3f(E.kn, zj[0], inv_wd, v0, v1, v2);
 #pragma unroll
-                for (int c = 0; c < C; ++c) A[s][c] = E.ok ? feature<O0, O1>(c, v0, v1, v2, zj) : 0.f;
+                for (int c = 0; c < C; ++c) A[s][c] = E.ok ? feature_f<O0, O1>(c, v0, v1, v2, zj) : 0.f;
             }
         };
         if (nblk > 0) {
