@@ -78,19 +78,37 @@ __device__ __forceinline__ float feature(int c, double v0, double v1, double v2,
     return (float)(v2 * ((double)zj[CH::Y] * (double)zj[CH::Y]) + v1 * (double)zj[CH::YY]);
 }
 
-// The same basis values and features with the offsets of z to the knots in
-// FP64, rounded once, and the rest in FP32 (a few FP32 units relative): for
-// the weight gradient, whose features enter only that layer's gradient sums
-// (FP32), not the later layers.
-__device__ __forceinline__ void bump3f(double2 kn, float z, double inv_w, float &v0, float &v1, float &v2)
+// Knot b as FP32 pairs (s_hi, s_lo, e_hi, e_lo) with s = s_hi + s_lo and e =
+// e_hi + e_lo to within FP64 rounding, and the basis scales in FP32, for the
+// weight gradient and the input bars: there the offsets of z to the knots are
+// (z - s_hi) - s_lo and (e_hi - z) + e_lo, each rounded to FP32 (the
+// subtraction of the nearby s_hi loses no leading bits), and the rest of the
+// basis is FP32: a few FP32 units relative, for features and adjoint terms
+// that enter only FP32 sums of their own layer, not the later layers.
+__device__ __forceinline__ float4 split_knot(double s, double e)
 {
-    const double zd = (double)z;
-    const float a = (float)((zd - kn.x) * inv_w), be = (float)((kn.y - zd) * inv_w);
+    const float sh = (float)s, eh = (float)e;
+    return make_float4(sh, (float)(s - (double)sh), eh, (float)(e - (double)eh));
+}
+
+struct BasisScale {
+    float w, k1, k2, k3;   // inv_w, 4 inv_w, 4 inv_w^2, 24 inv_w^3
+};
+__device__ __forceinline__ BasisScale basis_scale(double inv_w)
+{
+    return BasisScale{(float)inv_w, (float)(4.0 * inv_w), (float)(4.0 * inv_w * inv_w),
+                      (float)(24.0 * inv_w * inv_w * inv_w)};
+}
+
+// v, v', v'' of bump b at z, zero off the open support, a NaN input carried
+__device__ __forceinline__ void bump3f(float4 kn, float z, const BasisScale &bs, float &v0, float &v1, float &v2)
+{
+    const float a = ((z - kn.x) - kn.y) * bs.w, be = ((kn.z - z) + kn.w) * bs.w;
     const bool in = !(a <= 0.f) && !(be <= 0.f);
     const float t = a * be, d = be - a, t2 = t * t;
     v0 = in ? t2 * t2 : 0.f;
-    v1 = in ? (float)(4.0 * inv_w) * (t2 * t) * d : 0.f;
-    v2 = in ? (float)(4.0 * inv_w * inv_w) * t2 * (3.f * d * d - 2.f * t) : 0.f;
+    v1 = in ? bs.k1 * (t2 * t) * d : 0.f;
+    v2 = in ? bs.k2 * t2 * (3.f * d * d - 2.f * t) : 0.f;
 }
 
 template <int O0, int O1>
@@ -204,21 +222,18 @@ __device__ __forceinline__ int write_entries(unsigned short *ent, int lane, cons
     return tot;
 }
 
-// v', v'', v''' of bump b at FP32 input z (v[0] unused), for the adjoint of
-// the features in the input bars: the offsets of z to the knots, where FP32
-// would cancel, are taken in FP64 and rounded once; the polynomial in FP32
-// then costs a few FP32 units relative, below the FP32 rounding of the
-// input-bar sums it feeds. Zero off the open support, a NaN input carried.
-__device__ __forceinline__ void bump_d123f(double2 kn, float z, double inv_w, float *v)
+// v', v'', v''' of bump b at z (v[0] unused), for the adjoint of the
+// features in the input bars (split knots, FP32: see split_knot); zero off
+// the open support, a NaN input carried.
+__device__ __forceinline__ void bump_d123f(float4 kn, float z, const BasisScale &bs, float *v)
 {
-    const double zd = (double)z;
-    const float a = (float)((zd - kn.x) * inv_w), be = (float)((kn.y - zd) * inv_w);
+    const float a = ((z - kn.x) - kn.y) * bs.w, be = ((kn.z - z) + kn.w) * bs.w;
     const bool in = !(a <= 0.f) && !(be <= 0.f);
     const float t = a * be, d = be - a, t2 = t * t;
     v[0] = 0.f;
-    v[1] = in ? (float)(4.0 * inv_w) * (t2 * t) * d : 0.f;
-    v[2] = in ? (float)(4.0 * inv_w * inv_w) * t2 * (3.f * d * d - 2.f * t) : 0.f;
-    v[3] = in ? (float)(24.0 * inv_w * inv_w * inv_w) * t * d * (d * d - 3.f * t) : 0.f;
+    v[1] = in ? bs.k1 * (t2 * t) * d : 0.f;
+    v[2] = in ? bs.k2 * t2 * (3.f * d * d - 2.f * t) : 0.f;
+    v[3] = in ? bs.k3 * t * d * (d * d - 3.f * t) : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -426,7 +441,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
     constexpr int NS = NT16 > 4 ? 4 : (NT16 == 4 && C >= 4 ? 2 : NT16);
     constexpr int NP = NT16 / NS;
     __shared__ TcDxLds<O0, O1> lds[TW];
-    __shared__ double2 knots[MAXNB];
+    __shared__ float4 knots[MAXNB];    // split knots (split_knot)
     __shared__ int r0s_s[TW][TKJ], cnt_s[TW][TKJ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -434,8 +449,8 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
     int *r0s = r0s_s[wv], *cnts = cnt_s[wv];
     const int nb = gr.nb;
     const float inv_w = gr.inv_w, lo = gr.lo;
-    const double inv_wd = gr.inv_w_d;
-    if (threadIdx.x < nb) knots[threadIdx.x] = make_double2(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    if (threadIdx.x < nb) knots[threadIdx.x] = split_knot(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    const BasisScale bsc = basis_scale(gr.inv_w_d);
     __syncthreads();
     const int64_t ntiles = (n + TPT - 1) / TPT;
     const int nchunk = win / TKJ;
@@ -545,7 +560,7 @@ __global__ __launch_bounds__(TNT, tc_waves<NT16>()) void k_dx_tc(const float *__
                             Ab[c] = acc[c][r];
                             zd[c] = 0.f;
                         }
-                        bump_d123f(knots[b], zj[0], inv_wd, v);
+                        bump_d123f(knots[b], zj[0], bsc, v);
                         features_adjoint<float, O0, O1>(v, zj, Ab, zd);
 #pragma unroll
                         for (int c = 0; c < C; ++c) L.tm[4 * g + r][c][r16] = e < tot ? zd[c] : 0.f;
@@ -633,7 +648,7 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
     constexpr int TPH = TW / OG;                // waves per output group (tile phases)
     extern __shared__ __align__(16) float dsm[];
     __shared__ TcDwLds<O0, O1> lds[TW];
-    __shared__ double2 knots[MAXNB];
+    __shared__ float4 knots[MAXNB];    // split knots (split_knot)
     __shared__ int r0s_s[TW][TDJ], cnt_s[TW][TDJ];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -642,7 +657,6 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
     int *r0s = r0s_s[wv], *cnts = cnt_s[wv];
     const int nb = gr.nb;
     const float inv_w = gr.inv_w, lo = gr.lo;
-    const double inv_wd = gr.inv_w_d;
     // this block's input group and point slice. Blocks are dealt to the 8
     // XCDs in turn (block b to XCD b % 8); with xcd_map every input group of
     // a slice runs on one XCD, one after the other in its dispatch order, so
@@ -661,7 +675,8 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
     const int nin = min(TDI, win - i0);
     const int rows = nin * nb;
     float *grad = dsm + (size_t)wv * TDI * nb * 32;        // [row][32]
-    if (threadIdx.x < nb) knots[threadIdx.x] = make_double2(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    if (threadIdx.x < nb) knots[threadIdx.x] = split_knot(gr.s[threadIdx.x], gr.e[threadIdx.x]);
+    const BasisScale bsc = basis_scale(gr.inv_w_d);
     for (int e = lane; e < TDI * nb * 32; e += 64) grad[e] = 0.f;
     __syncthreads();
     const int64_t ps = (int64_t)sl * slice_pts;
@@ -744,7 +759,7 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
         // the last entry, multiplied as zero)
         struct Ent {
             int il;
-            double2 kn;
+            float4 kn;
             bool ok;
         };
         auto ent_of = [&](int eb_) {
@@ -765,7 +780,7 @@ __global__ __launch_bounds__(TNT, 2) void k_dw_tc(const float *__restrict__ zin,
 #pragma unroll
                 for (int c = 0; c < C; ++c) zj[c] = zz[c][s];
                 float v0, v1, v2;
-                bump3f(E.kn, zj[0], inv_wd, v0, v1, v2);
+                bump3f(E.kn, zj[0], bsc, v0, v1, v2);
 #pragma unroll
                 for (int c = 0; c < C; ++c) A[s][c] = E.ok ? feature_f<O0, O1>(c, v0, v1, v2, zj) : 0.f;
             }
